@@ -1,0 +1,189 @@
+"""Throughput of the tensorized-ACO iteration on one MI355X.
+
+A step is one whole iteration of the hot path over the workload: AdaIR tour
+construction for every ant (with tour lengths and successor/predecessor
+maps), best-so-far, elite weights, index-mapped deposit, evaporation and the
+next transition matrix.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  value = ant-steps per second over the whole iteration
+(m * (n-1) per step); roofline = the construct kernel's algorithmic HBM bytes
+per launch over its measured average duration; cpu_baseline = the CPU oracle
+on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "construct_counters.json")
+KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/philox.hpp"]
+
+
+def construct_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def construct_bytes(n, m):
+    """Algorithmic bytes of one construct launch: per ant-step one FP32 row of
+    P (4n), the tour entry written (4) and the distance gathered (4)."""
+    return m * (n - 1) * (4 * n + 8)
+
+
+def counter_traffic(n, m):
+    """HBM traffic per construct launch from committed rocprofv3 counters, or
+    None if they were taken on another workload or an older kernel."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != construct_source_hash() or c.get("n") != n or c.get("m") != m:
+        return None
+    return c.get("bytes_per_launch")
+
+
+def cpu_baseline(w, D, P, budget_s=15.0):
+    """The oracle as it is, on this host: construct for a sample of ants from
+    one P, plus one full update (deposit, evaporation, transition), scaled to
+    ant-steps per second of a whole iteration."""
+    import numpy as np
+
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    oracle.construct(P, D, 1, 0, np.arange(threads))
+    probe = time.perf_counter() - t0                 # one ant per thread
+    per_round = max(probe, 1e-3)
+    rounds = max(1, int((budget_s * 0.6) / per_round))
+    count = min(w.m, rounds * threads)
+    ants = np.arange(count)
+    t0 = time.perf_counter()
+    tours, lengths = oracle.construct(P, D, 1, 0, ants)
+    t_construct = time.perf_counter() - t0
+    # a full update on tours of the sample (the update's cost does not depend on which ants)
+    reps = int(np.ceil(w.m / count))
+    all_tours = np.tile(tours, (reps, 1))[:w.m]
+    all_len = np.tile(lengths, reps)[:w.m]
+    S = oracle.deposit_scale(D, w.m, w.Q)
+    tau = np.where(np.eye(w.n, dtype=bool), 0, np.float32(w.tau0)).astype(np.float32)
+    t0 = time.perf_counter()
+    delta = oracle.deposit(all_tours, all_len, None, w.Q, S)
+    tau = oracle.evaporate(tau, delta, w.rho, S)
+    oracle.transition(tau, D, w.alpha, w.beta, 1.5)
+    t_update = time.perf_counter() - t0
+    t_iter = t_construct * (w.m / count) + t_update
+    return {
+        "value": w.m * (w.n - 1) / t_iter,
+        "unit": "ant-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "construct of %d of %d ants (%.1f s) from one P, plus one full update "
+                  "(%.1f s), scaled to one whole iteration" % (count, w.m, t_construct, t_update),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="clustered-n5000-m5000")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the method is measured on one GPU's "
+              "share; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import aco_instances as inst
+    from paper_2404_04895_amd import Colony, gamma_schedule
+
+    w = inst.WORKLOADS[args.workload]
+    n, m, T = w.n, w.m, w.iters
+    D = w.dist(args.seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    col = Colony(torch.from_numpy(D).to(dev), w.alpha, w.beta, w.rho, w.Q, m, tau0=w.tau0,
+                 elite_k=w.elite_k, gamma_max=w.gamma_max, gamma_min=w.gamma_min)
+    stream = torch.cuda.current_stream()
+
+    def step(t, ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        col.construct(m, args.seed, t)
+        if ev is not None:
+            ev[1].record(stream)
+        col.update(gamma_schedule(t + 1, T, w.gamma_max, w.gamma_min))
+
+    col.transition(gamma_schedule(0, T, w.gamma_max, w.gamma_min))
+    for t in range(args.warmup):
+        step(t)
+    torch.cuda.synchronize()
+    P_host = col.P().cpu().numpy() if not args.no_cpu_baseline else None
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    construct_ms = [a.elapsed_time(b) for a, b in events]
+    avg_construct_s = sum(construct_ms) / len(construct_ms) / 1e3
+    ms_per_step = elapsed / args.steps * 1e3
+    ant_steps = m * (n - 1)
+    value = ant_steps * args.steps / elapsed
+    bytes_launch = construct_bytes(n, m)
+    achieved = bytes_launch / avg_construct_s / 1e9
+    traffic = counter_traffic(n, m)
+    _, best_len, best_iter = col.best()
+
+    line = {
+        "metric": "ant-steps/sec & % HBM peak; learned-vs-plain best-tour gap at equal time",
+        "value": value,
+        "unit": "ant-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "m": m, "alpha": w.alpha, "beta": w.beta,
+                   "rho": w.rho, "Q": w.Q, "cities": "%s, %d Gaussians sigma %g" % (
+                       w.family, w.clusters, w.sigma) if w.family != "uniform" else "uniform",
+                   "gamma": [w.gamma_max, w.gamma_min], "seed": args.seed},
+        "roofline": {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": bytes_launch,
+                     "avg_launch_ms": avg_construct_s * 1e3},
+        "construct_ant_steps_per_s": ant_steps / avg_construct_s,
+        "best_len": best_len,
+    }
+    col.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, D, P_host)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

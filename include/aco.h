@@ -1,0 +1,205 @@
+/*
+ * aco.h -- C ABI of the MI355X (gfx950) tensorized Ant Colony Optimization
+ * library for the symmetric Euclidean TSP (Yang, Jiang & Cheng, "Tensorized
+ * Ant Colony Optimization for GPU Acceleration", GECCO'24 Companion).
+ *
+ * One iteration of the method on one GPU:
+ *   transition  P = RowNormalized(tau^alpha * eta^beta)^(1/gamma)   Sec. 2.1 Eq. (1), Eq. (4)
+ *   construct   every ant builds a tour by Adaptive Independent
+ *               Roulette: next = argmax over unvisited j of P[c,j]*r_j  Sec. 2.2, Sec. 2.4
+ *   lengths     f(s) = closed tour length                           Sec. 2.3 (Eq. 3)
+ *   update      top-k elite, index-mapped deposit dTau = sum of A,
+ *               evaporation, then the next P                         Sec. 2.3 Eq. (2), Eq. (3)
+ *
+ * Conventions
+ *   - n cities, m ants.  Every matrix the library keeps is FP32, row-major,
+ *     n rows with a padded leading dimension ld = aco_leading_dim(n) (a multiple
+ *     of 64 floats); columns n..ld-1 are zero and never candidates.
+ *   - Device memory: the caller owns all of it.  The library carves every
+ *     buffer from one caller-provided workspace (aco_workspace_bytes) and calls
+ *     no device allocator.  The context object itself is a small host struct.
+ *   - Asynchrony: calls enqueue work on the HIP stream bound at creation and
+ *     return.  Exceptions that block the host: aco_create (validates the
+ *     distance matrix), aco_set_eta (validates eta), aco_run (final copy),
+ *     aco_best and aco_sync.
+ *   - Errors: every call returns an aco_status; nothing aborts or throws across
+ *     the ABI.  aco_last_error() gives a thread-local message for the last
+ *     failure.  Device faults surface as ACO_EDEVICE at the next blocking call.
+ *   - Random numbers: a counter-based Philox4x32-10 (Salmon, Moraes, Dror &
+ *     Shaw, SC'11) with key = (seed mod 2^32, seed >> 32).  The deviate r_j that
+ *     ant a draws for city j at step s of iteration t is word (j mod 4) of
+ *     counter (j/4, s, a, t), mapped to (2*(w>>9)+1) * 2^-24.  The start city
+ *     of ant a is (w0 * n) >> 32 with w0 word 0 of counter (0, 0, a, t).
+ *     Results therefore do not depend on launch shape or scheduling.
+ */
+#ifndef ACO_H
+#define ACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aco_ctx aco_ctx;
+
+typedef enum {
+    ACO_OK = 0,
+    ACO_EINVAL = -1,  /* bad argument, shape or input matrix            */
+    ACO_ENOMEM = -2,  /* workspace too small                             */
+    ACO_EDEVICE = -3, /* HIP runtime error or device fault               */
+    ACO_ESTATE = -4   /* call out of order (e.g. construct before any P) */
+} aco_status;
+
+/* Parameters beyond the four fixed at creation.  Defaults: tau0 = 1,
+ * elite_k = 0 (every ant deposits), gamma_max = 1.5, gamma_min = 1.0. */
+typedef struct {
+    float tau0;      /* initial pheromone on every edge, > 0                      */
+    int32_t elite_k; /* 0: all ants deposit; 0 < k <= m: the k shortest (Sec. 2.3) */
+    float gamma_max; /* AdaIR exponent at the first iteration (Sec. 2.4), > 0      */
+    float gamma_min; /* AdaIR exponent at the last iteration, > 0                  */
+} aco_params;
+
+/* Largest supported city count (the update keeps one FP64 row in LDS). */
+#define ACO_MAX_CITIES 16384
+
+/* Leading dimension (in elements) of every n-column matrix the library keeps:
+ * n rounded up to a multiple of 64.  Pure function. */
+int32_t aco_leading_dim(int32_t n);
+
+/* Bytes of device workspace needed for n cities and up to m_max ants per
+ * iteration, 256-byte aligned.  Pure function; 0 for invalid sizes. */
+size_t aco_workspace_bytes(int32_t n, int32_t m_max);
+
+/* Create a context for one TSP instance.
+ *   dist_dev   device pointer, n x n FP32 row-major (dense, leading dim n): the
+ *              distance matrix.  Must be symmetric (bitwise), zero on the
+ *              diagonal, finite and > 0 elsewhere.  Copied; the caller may free
+ *              it after the call returns.
+ *   n          3 <= n <= ACO_MAX_CITIES
+ *   alpha,beta >= 0, exponents of tau and eta in Eq. (1)
+ *   rho        evaporation rate in (0, 1]
+ *   Q          deposit numerator (Q / tour length), > 0
+ *   m_max      largest number of ants any later aco_construct may use, >= 1
+ *   workspace_dev, workspace_bytes   caller-owned device memory, at least
+ *              aco_workspace_bytes(n, m_max) bytes, 256-byte aligned; must stay
+ *              valid until aco_destroy.
+ *   hip_stream the hipStream_t every later call enqueues on (NULL: the null stream)
+ *   out        receives the context
+ * Initialises tau to tau0 and eta to 1/d (the plain heuristic of Eq. (1)).
+ * Blocks: validates dist and computes the deposit quantisation exponent.
+ * Errors: ACO_EINVAL for bad sizes, parameters or dist; ACO_ENOMEM for a small
+ * workspace; ACO_EDEVICE for HIP errors.  On error *out is NULL. */
+aco_status aco_create(const float* dist_dev, int32_t n, float alpha, float beta, float rho,
+                      float Q, int32_t m_max, void* workspace_dev, size_t workspace_bytes,
+                      void* hip_stream, aco_ctx** out);
+
+/* Re-bind the stream later calls enqueue on. */
+aco_status aco_set_stream(aco_ctx* ctx, void* hip_stream);
+
+/* Set tau0, elite_k and the gamma schedule; resets tau to tau0, clears the
+ * best-so-far and invalidates P (call aco_transition next).
+ * Errors: ACO_EINVAL for tau0 <= 0, elite_k < 0 or > m_max, gamma <= 0. */
+aco_status aco_set_params(aco_ctx* ctx, const aco_params* params);
+
+/* Replace the heuristic eta of Eq. (1) (default 1/d) by a caller matrix.
+ *   eta_dev  device pointer, n x n FP32 dense (leading dim n), or NULL to
+ *            return to 1/d.
+ * Blocks to validate: if any off-diagonal entry is not finite or not > 0 the
+ * context falls back to 1/d (aco_eta_active() then reports 0) and the call
+ * still returns ACO_OK.  Invalidates P. */
+aco_status aco_set_eta(aco_ctx* ctx, const float* eta_dev);
+
+/* 1 if a caller eta is in use, 0 if eta = 1/d. */
+int32_t aco_eta_active(const aco_ctx* ctx);
+
+/* Preprocessing, Sec. 2.1 Eq. (1), with the AdaIR exponent of Eq. (4) folded
+ * in: P_ij = (W_ij / sum_k W_ik)^(1/gamma), W_ij = tau_ij^alpha * eta_ij^beta,
+ * P_ii = 0; computed in FP64, stored FP32.  tau is not changed.
+ * Errors: ACO_EINVAL for gamma <= 0 or not finite. */
+aco_status aco_transition(aco_ctx* ctx, float gamma);
+
+/* Ant-system tensorization and AdaIR selection, Sec. 2.2 and Sec. 2.4: m ants
+ * (1 <= m <= m_max), each on its own wavefront, start at their random city and
+ * take n-1 steps; at each step the next city is the argmax over unvisited j of
+ * fl32(P[c,j] * r_j), ties to the smallest j.  Also computes each ant's closed
+ * tour length (FP64 sum in tour order, rounded to FP32) and the successor and
+ * predecessor maps the index-mapped deposit reads.
+ * Outputs (device views below): tours m x n int32, lengths m FP32.
+ * Errors: ACO_EINVAL for m out of range; ACO_ESTATE if no P is current. */
+aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter);
+
+/* Ant-path tensorization and pheromone update, Sec. 2.3 Eq. (2), Eq. (3),
+ * applied to the tours of the last aco_construct:
+ *   1. elite set: the elite_k shortest tours (length, then ant index), or all;
+ *   2. index-mapped deposit: every elite ant adds Q/L (quantised to an integer
+ *      multiple of 2^-S, aco_deposit_scale) on both orientations of each of its
+ *      tour edges, summed exactly in 64-bit integers (order-free);
+ *   3. evaporation: tau_ij <- fl32(fma(1-rho, tau_ij, dTau_ij)) in FP64;
+ *   4. P from the new tau with gamma_next (as aco_transition);
+ * and keeps the best-so-far tour (shortest; ties keep the earlier iteration,
+ * then the smaller ant).
+ * Errors: ACO_EINVAL for bad gamma_next; ACO_ESTATE without a construct since
+ * the last update. */
+aco_status aco_update(aco_ctx* ctx, float gamma_next);
+
+/* A whole run of `iters` iterations with m ants: P with gamma_0, then per
+ * iteration t construct (iteration counter = the context's running counter)
+ * and update with gamma_{t+1}, gamma following the cosine annealing schedule
+ * of Sec. 2.4 from gamma_max to gamma_min (aco_gamma_schedule).  Clears the
+ * best-so-far first; tau continues from its current state.  Blocks at the end
+ * and copies the best tour (n int32) and its length to host memory (either
+ * pointer may be NULL). */
+aco_status aco_run(aco_ctx* ctx, int32_t m, uint64_t seed, int32_t iters,
+                   int32_t* best_tour_host, float* best_len_host);
+
+/* Cosine annealing of gamma over T iterations (Sec. 2.4):
+ * gamma_t = gmin + (gmax - gmin) * (1 + cos(pi * t / (T-1))) / 2, computed in
+ * FP64 and rounded to FP32; t is clamped to T-1; T <= 1 gives gmax. */
+float aco_gamma_schedule(int32_t t, int32_t T, float gamma_max, float gamma_min);
+
+/* Borrowed device views into the workspace, valid until the next call that
+ * writes them or aco_destroy.  tau and P are n x ld; tours m_max x n (rows of
+ * the last construct); lengths m_max. */
+const float* aco_pheromone(const aco_ctx* ctx);
+const float* aco_transition_matrix(const aco_ctx* ctx);
+const int32_t* aco_tours(const aco_ctx* ctx);
+const float* aco_lengths(const aco_ctx* ctx);
+
+/* Exponent S of the deposit quantisation: the largest S with
+ * m_max * Q / L_lb * 2^S < 2^62, L_lb = sum over cities of the nearest
+ * neighbour distance (FP64, ascending city order).  -1 for NULL. */
+int32_t aco_deposit_scale(const aco_ctx* ctx);
+
+/* Best-so-far tour, its length and its iteration (blocks).  Any pointer may be
+ * NULL.  Length is +inf and iteration -1 before any update. */
+aco_status aco_best(aco_ctx* ctx, int32_t* tour_host, float* len_host, int32_t* iter_host);
+
+/* Checkpoint and resume: copy tau (n x ld FP32, device) and the iteration
+ * counter out of / into the context.  aco_set_state invalidates P.  The
+ * generator is stateless, so a resumed run repeats an uninterrupted one. */
+aco_status aco_get_state(const aco_ctx* ctx, float* tau_dev_out, uint32_t* iter_out);
+aco_status aco_set_state(aco_ctx* ctx, const float* tau_dev, uint32_t iter);
+
+/* Diagnostic: write the deviates r_j, j = 0..count-1, that ant a draws at step
+ * s of iteration t (see the header comment) to out_dev (device, count FP32),
+ * on hip_stream.  Errors: ACO_EINVAL for count < 0. */
+aco_status aco_uniforms(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
+                        int32_t count, float* out_dev, void* hip_stream);
+
+/* Block until all work enqueued by this context has finished; reports device
+ * errors as ACO_EDEVICE. */
+aco_status aco_sync(aco_ctx* ctx);
+
+/* Free the host context (the workspace stays the caller's). NULL is a no-op. */
+void aco_destroy(aco_ctx* ctx);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* aco_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACO_H */

@@ -1,0 +1,216 @@
+"""Tensorized Ant Colony Optimization for the Euclidean TSP on MI355X (gfx950).
+
+Python binding of libaco.so (C ABI: include/aco.h).  This layer only marshals
+arguments: every step of an iteration runs in the library's HIP kernels.
+PyTorch provides the device memory (one workspace tensor per colony) and the
+stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native
+from ._native import AcoError, AcoParams, check, lib
+
+__all__ = ["Colony", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
+           "leading_dim", "MAX_CITIES"]
+
+MAX_CITIES = _native.MAX_CITIES
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def leading_dim(n: int) -> int:
+    return lib().aco_leading_dim(n)
+
+
+def workspace_bytes(n: int, m_max: int) -> int:
+    return lib().aco_workspace_bytes(n, m_max)
+
+
+def gamma_schedule(t: int, T: int, gamma_max: float, gamma_min: float) -> float:
+    return lib().aco_gamma_schedule(t, T, gamma_max, gamma_min)
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def uniforms(seed: int, iter: int, ant: int, step: int, count: int, device="cuda", stream=None):
+    """The deviates r_j (j < count) ant `ant` draws at `step` of `iter`, from the device generator."""
+    torch = _torch()
+    out = torch.empty(count, dtype=torch.float32, device=device)
+    check(lib().aco_uniforms(seed, iter, ant, step, count, ctypes.c_void_p(out.data_ptr()),
+                             _stream_handle(stream)), "aco_uniforms")
+    return out
+
+
+class Colony:
+    """One TSP instance and its pheromone state on one GPU.
+
+    dist: (n, n) float32 distance matrix, a CUDA tensor or anything numpy accepts.
+    """
+
+    def __init__(self, dist, alpha: float, beta: float, rho: float, Q: float = 1.0,
+                 m_max: int | None = None, *, tau0: float = 1.0, elite_k: int = 0,
+                 gamma_max: float = 1.5, gamma_min: float = 1.0, device="cuda", stream=None):
+        torch = _torch()
+        if not isinstance(dist, torch.Tensor):
+            dist = torch.from_numpy(np.ascontiguousarray(dist, dtype=np.float32))
+        if dist.device.type != "cuda":
+            dist = dist.to(device)
+        dist = dist.to(torch.float32).contiguous()
+        if dist.dim() != 2 or dist.shape[0] != dist.shape[1]:
+            raise ValueError("dist must be a square matrix")
+        n = int(dist.shape[0])
+        self.n = n
+        self.m_max = int(m_max if m_max is not None else n)
+        self.device = dist.device
+        self.ld = leading_dim(n)
+        self._stream = stream
+        self._ctx = None
+        nbytes = workspace_bytes(n, self.m_max)
+        if nbytes == 0:
+            check(_native.ACO_EINVAL if n < 3 or n > MAX_CITIES else _native.ACO_EINVAL,
+                  "aco_workspace_bytes(n=%d, m_max=%d)" % (n, self.m_max))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace tensor is not 256-byte aligned")
+        ctx = ctypes.c_void_p()
+        check(lib().aco_create(ctypes.c_void_p(dist.data_ptr()), n, alpha, beta, rho, Q,
+                               self.m_max, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                               _stream_handle(stream), ctypes.byref(ctx)), "aco_create")
+        self._ctx = ctx
+        self.alpha, self.beta, self.rho, self.Q = alpha, beta, rho, Q
+        self.params = AcoParams(tau0, elite_k, gamma_max, gamma_min)
+        if (tau0, elite_k, gamma_max, gamma_min) != (1.0, 0, 1.5, 1.0):
+            self.set_params(tau0=tau0, elite_k=elite_k, gamma_max=gamma_max,
+                            gamma_min=gamma_min)
+
+    # ---- lifetime ---------------------------------------------------------
+    def close(self):
+        if self._ctx is not None:
+            lib().aco_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- configuration ----------------------------------------------------
+    def set_params(self, *, tau0=None, elite_k=None, gamma_max=None, gamma_min=None):
+        p = AcoParams(self.params.tau0 if tau0 is None else tau0,
+                      self.params.elite_k if elite_k is None else elite_k,
+                      self.params.gamma_max if gamma_max is None else gamma_max,
+                      self.params.gamma_min if gamma_min is None else gamma_min)
+        check(lib().aco_set_params(self._ctx, ctypes.byref(p)), "aco_set_params")
+        self.params = p
+
+    def set_eta(self, eta):
+        """Replace eta = 1/d by a caller heuristic ((n, n) float32), or None for 1/d.
+        Returns True if the heuristic is in use (False: it was rejected, 1/d is used)."""
+        torch = _torch()
+        if eta is None:
+            check(lib().aco_set_eta(self._ctx, None), "aco_set_eta")
+            return False
+        if not isinstance(eta, torch.Tensor):
+            eta = torch.from_numpy(np.ascontiguousarray(eta, dtype=np.float32))
+        eta = eta.to(self.device, torch.float32).contiguous()
+        check(lib().aco_set_eta(self._ctx, ctypes.c_void_p(eta.data_ptr())), "aco_set_eta")
+        return bool(lib().aco_eta_active(self._ctx))
+
+    def set_stream(self, stream):
+        self._stream = stream
+        check(lib().aco_set_stream(self._ctx, _stream_handle(stream)), "aco_set_stream")
+
+    # ---- the iteration ----------------------------------------------------
+    def transition(self, gamma: float):
+        check(lib().aco_transition(self._ctx, gamma), "aco_transition")
+
+    def construct(self, m: int, seed: int, iter: int):
+        check(lib().aco_construct(self._ctx, m, seed, iter), "aco_construct")
+
+    def update(self, gamma_next: float):
+        check(lib().aco_update(self._ctx, gamma_next), "aco_update")
+
+    def run(self, m: int, seed: int, iters: int):
+        tour = np.zeros(self.n, np.int32)
+        length = ctypes.c_float()
+        check(lib().aco_run(self._ctx, m, seed, iters, tour.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.byref(length)), "aco_run")
+        return tour, float(length.value)
+
+    def best(self):
+        tour = np.zeros(self.n, np.int32)
+        length = ctypes.c_float()
+        it = ctypes.c_int32()
+        check(lib().aco_best(self._ctx, tour.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(length), ctypes.byref(it)), "aco_best")
+        return tour, float(length.value), int(it.value)
+
+    def sync(self):
+        check(lib().aco_sync(self._ctx), "aco_sync")
+
+    @property
+    def deposit_scale(self) -> int:
+        return lib().aco_deposit_scale(self._ctx)
+
+    # ---- device views -----------------------------------------------------
+    def _view(self, ptr, dtype, shape):
+        torch = _torch()
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        count = int(np.prod(shape))
+        off = ptr - self.workspace.data_ptr()
+        assert 0 <= off and off + count * itemsize <= self.workspace.numel()
+        return self.workspace[off:off + count * itemsize].view(dtype).view(*shape)
+
+    def tau_padded(self):
+        return self._view(lib().aco_pheromone(self._ctx), _torch().float32, (self.n, self.ld))
+
+    def P_padded(self):
+        return self._view(lib().aco_transition_matrix(self._ctx), _torch().float32,
+                          (self.n, self.ld))
+
+    def tau(self):
+        return self.tau_padded()[:, :self.n]
+
+    def P(self):
+        return self.P_padded()[:, :self.n]
+
+    def tours(self, m: int | None = None):
+        t = self._view(lib().aco_tours(self._ctx), _torch().int32, (self.m_max, self.n))
+        return t if m is None else t[:m]
+
+    def lengths(self, m: int | None = None):
+        L = self._view(lib().aco_lengths(self._ctx), _torch().float32, (self.m_max,))
+        return L if m is None else L[:m]
+
+    # ---- checkpoint -------------------------------------------------------
+    def get_state(self):
+        torch = _torch()
+        tau = torch.empty((self.n, self.ld), dtype=torch.float32, device=self.device)
+        it = ctypes.c_uint32()
+        check(lib().aco_get_state(self._ctx, ctypes.c_void_p(tau.data_ptr()), ctypes.byref(it)),
+              "aco_get_state")
+        return tau, int(it.value)
+
+    def set_state(self, tau_padded, iter: int):
+        tau_padded = tau_padded.to(self.device).contiguous()
+        assert tuple(tau_padded.shape) == (self.n, self.ld)
+        check(lib().aco_set_state(self._ctx, ctypes.c_void_p(tau_padded.data_ptr()), iter),
+              "aco_set_state")

@@ -1,0 +1,86 @@
+"""ctypes declarations for libaco.so (the C ABI in include/aco.h).
+
+Loading fails loudly if the library has not been built: there is no other
+implementation behind these names.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaco.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "aco.h")
+
+ACO_OK, ACO_EINVAL, ACO_ENOMEM, ACO_EDEVICE, ACO_ESTATE = 0, -1, -2, -3, -4
+STATUS_NAMES = {0: "ACO_OK", -1: "ACO_EINVAL", -2: "ACO_ENOMEM", -3: "ACO_EDEVICE",
+                -4: "ACO_ESTATE"}
+MAX_CITIES = 16384
+
+
+class AcoParams(ctypes.Structure):
+    _fields_ = [("tau0", ctypes.c_float), ("elite_k", ctypes.c_int32),
+                ("gamma_max", ctypes.c_float), ("gamma_min", ctypes.c_float)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_f32 = ctypes.c_float
+
+SIGNATURES = {
+    "aco_leading_dim": (_i32, [_i32]),
+    "aco_workspace_bytes": (ctypes.c_size_t, [_i32, _i32]),
+    "aco_create": (_i32, [_vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp, ctypes.c_size_t, _vp,
+                          ctypes.POINTER(_vp)]),
+    "aco_set_stream": (_i32, [_vp, _vp]),
+    "aco_set_params": (_i32, [_vp, ctypes.POINTER(AcoParams)]),
+    "aco_set_eta": (_i32, [_vp, _vp]),
+    "aco_eta_active": (_i32, [_vp]),
+    "aco_transition": (_i32, [_vp, _f32]),
+    "aco_construct": (_i32, [_vp, _i32, _u64, _u32]),
+    "aco_update": (_i32, [_vp, _f32]),
+    "aco_run": (_i32, [_vp, _i32, _u64, _i32, _vp, _vp]),
+    "aco_gamma_schedule": (_f32, [_i32, _i32, _f32, _f32]),
+    "aco_pheromone": (_vp, [_vp]),
+    "aco_transition_matrix": (_vp, [_vp]),
+    "aco_tours": (_vp, [_vp]),
+    "aco_lengths": (_vp, [_vp]),
+    "aco_deposit_scale": (_i32, [_vp]),
+    "aco_best": (_i32, [_vp, _vp, _vp, _vp]),
+    "aco_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
+    "aco_set_state": (_i32, [_vp, _vp, _u32]),
+    "aco_uniforms": (_i32, [_u64, _u32, _u32, _u32, _i32, _vp, _vp]),
+    "aco_sync": (_i32, [_vp]),
+    "aco_destroy": (None, [_vp]),
+    "aco_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libaco.so is not built (expected at %s); run __graft_entry__.build() or "
+                "python paper_2404_04895_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class AcoError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().aco_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+
+
+def check(status, where):
+    if status != ACO_OK:
+        raise AcoError(status, where)

@@ -1,0 +1,80 @@
+// Internal declarations shared by the kernels' launchers and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "aco.h"
+
+// Largest row the update kernel keeps in LDS (FP64 entries).
+#define ACO_LDS_ROW_MAX ACO_MAX_CITIES
+
+namespace aco {
+
+// Best-so-far record kept on the device (written by the best-tour kernel).
+struct BestRecord {
+    float len;     // +inf before the first update
+    int32_t iter;  // iteration that produced it, -1 before
+    int32_t ant;   // ant index within that iteration
+    int32_t pad;
+};
+
+// Device buffers carved from the caller's workspace.
+struct Buffers {
+    float* dist;        // n x ld
+    float* tau;         // n x ld
+    float* P;           // n x ld
+    float* eta;         // n x ld (caller heuristic, when active)
+    int32_t* tours;     // m_max x n
+    float* lengths;     // m_max
+    int32_t* succ;      // n x m_max: succ[c*m_max + a] = city after c in ant a's tour
+    int32_t* pred;      // n x m_max: pred[c*m_max + a] = city before c
+    int64_t* weight;    // m_max: quantised deposit of each ant (0 if not elite)
+    int32_t* best_tour; // n
+    BestRecord* best;   // 1
+    float* row_min;     // n: nearest-neighbour distance of each city
+    double* lower_bound;// 1: sum of row_min
+    uint32_t* flags;    // 4 validation flags
+};
+
+struct Layout {
+    size_t off_dist, off_tau, off_P, off_eta, off_tours, off_lengths, off_succ, off_pred,
+        off_weight, off_best_tour, off_best, off_row_min, off_lower_bound, off_flags, total;
+};
+
+Layout make_layout(int32_t n, int32_t ld, int32_t m_max);
+Buffers carve(char* base, const Layout& L);
+
+// Validation flag bits (for the input check kernels).
+enum : uint32_t {
+    kFlagNotFinite = 1u,
+    kFlagNotPositive = 2u,
+    kFlagAsymmetric = 4u,
+    kFlagDiagonal = 8u,
+};
+
+// ---- launchers (each enqueues on `stream`, returns the launch status) ----
+hipError_t launch_init_state(const float* dist_dense, int32_t n, int32_t ld, float tau0,
+                             const Buffers& B, hipStream_t stream);
+hipError_t launch_reset_tau(int32_t n, int32_t ld, float tau0, const Buffers& B,
+                            hipStream_t stream);
+hipError_t launch_validate(const float* mat_dense, int32_t n, bool check_symmetry,
+                           bool want_row_min, const Buffers& B, hipStream_t stream);
+hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,
+                              hipStream_t stream);
+hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
+                            uint64_t seed, uint32_t iter, hipStream_t stream);
+hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, float Q,
+                                  int32_t S, hipStream_t stream);
+hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
+                       hipStream_t stream);
+hipError_t launch_clear_best(const Buffers& B, hipStream_t stream);
+hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
+                       bool apply_deposit, bool use_eta, float alpha, float beta, float rho,
+                       int32_t S, float gamma, hipStream_t stream);
+hipError_t launch_uniforms(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
+                           int32_t count, float* out, hipStream_t stream);
+hipError_t prepare_kernels();
+
+}  // namespace aco

@@ -1,0 +1,47 @@
+// Device-side counter-based generator for the AdaIR deviates (Sec. 2.4).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  In the construct loop
+// the key and three of the four counter words -- step, ant, iteration -- are
+// the same for the whole wavefront, and only the city-block word varies by
+// lane, so the compiler keeps the key schedule and the uniform half of the
+// first round in scalar registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aco {
+
+struct PhiloxOut {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ PhiloxOut philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                             uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u;  // round multiplier for word 0
+    constexpr uint32_t kMulB = 0xCD9E8D57u;  // round multiplier for word 2
+    constexpr uint32_t kBumpA = 0x9E3779B9u; // key schedule increments
+    constexpr uint32_t kBumpB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(x0) * kMulA;
+        const uint64_t pb = static_cast<uint64_t>(x2) * kMulB;
+        const uint32_t rk0 = k0 + static_cast<uint32_t>(r) * kBumpA;
+        const uint32_t rk1 = k1 + static_cast<uint32_t>(r) * kBumpB;
+        x0 = static_cast<uint32_t>(pb >> 32) ^ x1 ^ rk0;
+        x1 = static_cast<uint32_t>(pb);
+        x2 = static_cast<uint32_t>(pa >> 32) ^ x3 ^ rk1;
+        x3 = static_cast<uint32_t>(pa);
+    }
+    return PhiloxOut{x0, x1, x2, x3};
+}
+
+// (2*(w >> 9) + 1) * 2^-24 without a conversion: OR the top 23 bits into the
+// mantissa of 1.0f, giving 1 + k*2^-23 in [1, 2), then subtract 1 - 2^-24.
+// The difference (2k+1)*2^-24 has at most 24 significant bits, so the FP32
+// subtraction is exact.
+__device__ __forceinline__ float unit_from_word(uint32_t w) {
+    return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
+}
+
+}  // namespace aco
