@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--workload", default="clustered-n5000-m5000")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing (a "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the method is measured on one GPU's "
@@ -130,6 +133,12 @@ def main():
             ev[1].record(stream)
         col.update(gamma_schedule(t + 1, T, w.gamma_max, w.gamma_min))
 
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     col.transition(gamma_schedule(0, T, w.gamma_max, w.gamma_min))
     for t in range(args.warmup):
         step(t)
