@@ -23,17 +23,24 @@ namespace {
 
 constexpr int kWave = 64;
 
-// Score one candidate; key = FP32 bit pattern of the score (scores are >= +0,
-// so bit patterns order like the values), -1 for a visited city.  Within a
-// lane candidates arrive in increasing j, so a strict compare keeps the
-// smallest j among equal scores.
-__device__ __forceinline__ void consider(float p, uint32_t word, bool taken, int32_t j,
-                                         int32_t& best_key, int32_t& best_j) {
-    const float score = p * unit_from_word(word);
-    const int32_t key = taken ? -1 : __float_as_int(score);
+// Score one candidate.  key = FP32 bit pattern of fl32(P[c,j] * r_j) with the
+// city's visited bit in the sign position: scores are >= +0, so unvisited keys
+// are >= 0 and order like the scores, while visited keys are negative and can
+// never beat the initial -1.  Within a lane candidates arrive in increasing j,
+// so a strict compare keeps the smallest j among equal scores.  The winner is
+// recorded as `id` = j - 4*lane, which is the same for every lane of the wave
+// (a scalar operand).
+__device__ __forceinline__ void consider(float p, uint32_t word, uint32_t taken_sign, int32_t id,
+                                         int32_t& best_key, int32_t& best_id) {
+    // 0x3F800000 | (word >> 9): the funnel shift brings 0x7F in above the top
+    // 23 bits of the word, i.e. 1 + k*2^-23; minus (1 - 2^-24) gives the
+    // deviate (2k+1)*2^-24 exactly.
+    const float unit = __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, word, 9)) - 0x1.fffffep-1f;
+    const float score = p * unit;
+    const int32_t key = static_cast<int32_t>(__float_as_uint(score) | taken_sign);
     if (key > best_key) {
         best_key = key;
-        best_j = j;
+        best_id = id;
     }
 }
 
@@ -65,20 +72,27 @@ __global__ __launch_bounds__(kWave) void construct_kernel(
     int32_t cur = start;
     double len = 0.0;
 
+    const int32_t nchunk = (nblk + kWave - 1) / kWave;
     for (int32_t s = 1; s < n; ++s) {
         const float* row = P + static_cast<size_t>(cur) * ld;
         int32_t best_key = -1;
-        int32_t best_j = 0x7FFFFFFF;
-        for (int32_t b = lane; b < nblk; b += kWave) {
-            const float4 p = *reinterpret_cast<const float4*>(row + 4 * b);
-            const PhiloxOut r = philox10(static_cast<uint32_t>(b), static_cast<uint32_t>(s),
-                                         static_cast<uint32_t>(ant), iter, key0, key1);
-            const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
-            consider(p.x, r.w0, taken & 1u, 4 * b + 0, best_key, best_j);
-            consider(p.y, r.w1, taken & 2u, 4 * b + 1, best_key, best_j);
-            consider(p.z, r.w2, taken & 4u, 4 * b + 2, best_key, best_j);
-            consider(p.w, r.w3, taken & 8u, 4 * b + 3, best_key, best_j);
+        int32_t best_id = 0;
+        for (int32_t k = 0; k < nchunk; ++k) {
+            const int32_t b = k * kWave + lane;
+            if (b < nblk) {
+                const float4 p = *reinterpret_cast<const float4*>(row + 4 * b);
+                const PhiloxOut r = philox10_block(static_cast<uint32_t>(b),
+                                                   static_cast<uint32_t>(s),
+                                                   static_cast<uint32_t>(ant), iter, key0, key1);
+                const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
+                const int32_t base = 4 * kWave * k;  // j = 4*lane + base + e
+                consider(p.x, r.w0, taken << 31, base + 0, best_key, best_id);
+                consider(p.y, r.w1, (taken << 30) & 0x80000000u, base + 1, best_key, best_id);
+                consider(p.z, r.w2, (taken << 29) & 0x80000000u, base + 2, best_key, best_id);
+                consider(p.w, r.w3, (taken << 28) & 0x80000000u, base + 3, best_key, best_id);
+            }
         }
+        int32_t best_j = (best_key >= 0) ? 4 * lane + best_id : 0x7FFFFFFF;
         // Wave argmax: larger key wins, equal keys go to the smaller city.
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) {

@@ -36,6 +36,66 @@ __device__ __forceinline__ PhiloxOut philox10(uint32_t x0, uint32_t x1, uint32_t
     return PhiloxOut{x0, x1, x2, x3};
 }
 
+// Three-input XOR in one gfx950 VALU instruction (v_bitop3_b32 with truth
+// table 0x96 = a ^ b ^ c, which is symmetric in its operands).  c is the
+// wave-uniform round key and is read from a scalar register.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// Philox4x32-10 for the counter (block, step, ant, iter) of the construct
+// loop, where only `block` differs between lanes.  Rounds 1 and 2 are left to
+// the compiler, which evaluates their wave-uniform halves on the scalar unit;
+// from round 3 on all four words differ by lane and each new word 0 / word 2
+// is one 32x32->64 multiply plus one three-input XOR.
+__device__ __forceinline__ PhiloxOut philox10_block(uint32_t block, uint32_t step, uint32_t ant,
+                                                   uint32_t iter, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u;
+    constexpr uint32_t kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kBumpA = 0x9E3779B9u;
+    constexpr uint32_t kBumpB = 0xBB67AE85u;
+    uint32_t x0 = block, x1 = step, x2 = ant, x3 = iter;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(x0) * kMulA;
+        const uint64_t pb = static_cast<uint64_t>(x2) * kMulB;
+        const uint32_t rk0 = k0 + static_cast<uint32_t>(r) * kBumpA;
+        const uint32_t rk1 = k1 + static_cast<uint32_t>(r) * kBumpB;
+        x0 = static_cast<uint32_t>(pb >> 32) ^ (x1 ^ rk0);
+        x1 = static_cast<uint32_t>(pb);
+        x2 = static_cast<uint32_t>(pa >> 32) ^ (x3 ^ rk1);
+        x3 = static_cast<uint32_t>(pa);
+    }
+    // after round 2, word 3 (low half of word 0 times kMulA, word 0 being
+    // uniform after round 1) is still uniform: fold it into the key first.
+    {
+        const uint64_t pa = static_cast<uint64_t>(x0) * kMulA;
+        const uint64_t pb = static_cast<uint64_t>(x2) * kMulB;
+        const uint32_t n0 = xor3_vvs(static_cast<uint32_t>(pb >> 32), x1, k0 + 2u * kBumpA);
+        const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ (x3 ^ (k1 + 2u * kBumpB));
+        x0 = n0;
+        x1 = static_cast<uint32_t>(pb);
+        x2 = n2;
+        x3 = static_cast<uint32_t>(pa);
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(x0) * kMulA;
+        const uint64_t pb = static_cast<uint64_t>(x2) * kMulB;
+        const uint32_t n0 = xor3_vvs(static_cast<uint32_t>(pb >> 32), x1,
+                                     k0 + static_cast<uint32_t>(r) * kBumpA);
+        const uint32_t n2 = xor3_vvs(static_cast<uint32_t>(pa >> 32), x3,
+                                     k1 + static_cast<uint32_t>(r) * kBumpB);
+        x0 = n0;
+        x1 = static_cast<uint32_t>(pb);
+        x2 = n2;
+        x3 = static_cast<uint32_t>(pa);
+    }
+    return PhiloxOut{x0, x1, x2, x3};
+}
+
 // (2*(w >> 9) + 1) * 2^-24 without a conversion: OR the top 23 bits into the
 // mantissa of 1.0f, giving 1 + k*2^-23 in [1, 2), then subtract 1 - 2^-24.
 // The difference (2k+1)*2^-24 has at most 24 significant bits, so the FP32
