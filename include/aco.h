@@ -182,6 +182,102 @@ aco_status aco_best(aco_ctx* ctx, int32_t* tour_host, float* len_host, int32_t* 
 aco_status aco_get_state(const aco_ctx* ctx, float* tau_dev_out, uint32_t* iter_out);
 aco_status aco_set_state(aco_ctx* ctx, const float* tau_dev, uint32_t iter);
 
+/* Construct schedules: how many lanes of a 64-lane wavefront build one ant
+ * (Sec. 2.2's function mapping over ants), and whether each ant keeps the
+ * sorted list of 4-city blocks that still hold an unvisited city (a step then
+ * scans only those).  Every schedule gives bit-identical results: the
+ * generator is keyed by city block, not by lane.  ACO_SCHED_AUTO picks by
+ * size: 16 lanes up to 64 cities, 32 up to 128, 64 up to 256, then 64 with
+ * the list. */
+#define ACO_SCHED_AUTO (-1)
+#define ACO_SCHED_G16 0      /* 16 lanes per ant, 4 ants per wavefront */
+#define ACO_SCHED_G32 1      /* 32 lanes per ant, 2 ants per wavefront */
+#define ACO_SCHED_G32_LIVE 2 /* 32 lanes per ant, live-block list      */
+#define ACO_SCHED_G64 3      /* one ant per wavefront                  */
+#define ACO_SCHED_G64_LIVE 4 /* one ant per wavefront, live-block list */
+
+/* Select the construct schedule of this context (ACO_SCHED_*).
+ * Errors: ACO_EINVAL for an unknown code. */
+aco_status aco_set_schedule(aco_ctx* ctx, int32_t schedule);
+
+/* ------------------------------------------------------------------------ */
+/* Batched engine: many independent instances of uneven size advanced        */
+/* together, one persistent construct launch and one row-update launch per  */
+/* iteration (optionally replayed from a captured hipGraph).  Instance i      */
+/* evolves exactly -- bit for bit -- as aco_create(dist_i, n_i, alpha, beta, */
+/* rho, Q, m_max = m_i) + aco_set_params(params) + aco_run(m_i, seed_i, ...)  */
+/* would alone.                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct aco_batch aco_batch;
+
+/* One row of a schedule table: instances with n <= n_max (the first row that
+ * matches, rows sorted by n_max) use `schedule`. */
+typedef struct {
+    int32_t n_max;
+    int32_t schedule;
+} aco_schedule_entry;
+
+/* Device views of one member of a batch (borrowed; valid until destroy). */
+typedef struct {
+    int32_t n, ld, m, deposit_scale, schedule;
+    const float* tau;        /* n x ld */
+    const float* P;          /* n x ld */
+    const int32_t* tours;    /* m x n (last iteration) */
+    const float* lengths;    /* m */
+    const int32_t* best_tour;/* n */
+} aco_batch_view;
+
+/* Bytes of device workspace for `count` instances of n_host[i] cities and
+ * m_host[i] ants (host arrays).  0 for invalid sizes. */
+size_t aco_batch_workspace_bytes(const int32_t* n_host, const int32_t* m_host, int32_t count);
+
+/* Create a batch.
+ *   dists_dev          one device buffer; instance i's dense n_i x n_i FP32
+ *                      distance matrix starts at element dist_offsets_host[i]
+ *                      (same requirements as aco_create's dist; copied)
+ *   n_host, m_host     cities and ants of each instance (host, count entries)
+ *   seeds_host         generator seed of each instance (host)
+ *   alpha..Q, params   shared by all instances (params NULL: defaults;
+ *                      elite_k >= m_i means all ants for instance i)
+ *   workspace          caller-owned device memory, 256-byte aligned, at least
+ *                      aco_batch_workspace_bytes(); valid until destroy
+ *   hip_stream         the stream every call enqueues on; a non-null stream
+ *                      is needed for graph replay
+ * Blocks to validate the instances.  Errors as aco_create. */
+aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_host,
+                            const int32_t* n_host, const int32_t* m_host,
+                            const uint64_t* seeds_host, int32_t count, float alpha, float beta,
+                            float rho, float Q, const aco_params* params, void* workspace_dev,
+                            size_t workspace_bytes, void* hip_stream, aco_batch** out);
+
+/* Install a schedule table (host array, copied) and the number of persistent
+ * construct wavefronts (0: 4096).  Instances no row covers use ACO_SCHED_AUTO.
+ * Blocks (uploads the task queue).  Errors: ACO_EINVAL for unknown codes. */
+aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table,
+                                   int32_t entries, int32_t persistent_waves);
+
+/* Run `iters` iterations on every instance, from its current pheromone state
+ * and the batch's running iteration counter, with the cosine gamma schedule
+ * over `iters` (as aco_run).  Clears the best-so-far records first.  Enqueues
+ * and returns; use_graph != 0 (with a non-null stream) captures one iteration
+ * once and replays it.  Errors: ACO_EINVAL for iters outside [0, 65535]. */
+aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t use_graph);
+
+/* Best-so-far length and iteration of every instance (host arrays of count
+ * entries) and the best tours concatenated in instance order (sum of n_i
+ * entries); any pointer may be NULL.  Blocks. */
+aco_status aco_batch_best(aco_batch* b, float* lens_host, int32_t* iters_host,
+                          int32_t* tours_host);
+
+/* Device views of instance i.  Errors: ACO_EINVAL for i out of range. */
+aco_status aco_batch_instance(const aco_batch* b, int32_t i, aco_batch_view* view);
+
+/* Block until the batch's enqueued work is done; reports device errors. */
+aco_status aco_batch_sync(aco_batch* b);
+
+/* Free the host object (the workspace stays the caller's). NULL is a no-op. */
+void aco_batch_destroy(aco_batch* b);
+
 /* Diagnostic: write the deviates r_j, j = 0..count-1, that ant a draws at step
  * s of iteration t (see the header comment) to out_dev (device, count FP32),
  * on hip_stream.  Errors: ACO_EINVAL for count < 0. */

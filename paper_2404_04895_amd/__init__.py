@@ -12,10 +12,12 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import AcoError, AcoParams, check, lib
+from ._native import (SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64,
+                      SCHED_G64_LIVE, SCHEDULES, AcoError, AcoParams, BatchView, ScheduleEntry,
+                      check, lib)
 
-__all__ = ["Colony", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
-           "leading_dim", "MAX_CITIES"]
+__all__ = ["Colony", "Batch", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
+           "leading_dim", "MAX_CITIES", "SCHEDULES", "SCHED_AUTO"]
 
 MAX_CITIES = _native.MAX_CITIES
 
@@ -134,6 +136,9 @@ class Colony:
         check(lib().aco_set_eta(self._ctx, ctypes.c_void_p(eta.data_ptr())), "aco_set_eta")
         return bool(lib().aco_eta_active(self._ctx))
 
+    def set_schedule(self, schedule: int):
+        check(lib().aco_set_schedule(self._ctx, schedule), "aco_set_schedule")
+
     def set_stream(self, stream):
         self._stream = stream
         check(lib().aco_set_stream(self._ctx, _stream_handle(stream)), "aco_set_stream")
@@ -214,3 +219,108 @@ class Colony:
         assert tuple(tau_padded.shape) == (self.n, self.ld)
         check(lib().aco_set_state(self._ctx, ctypes.c_void_p(tau_padded.data_ptr()), iter),
               "aco_set_state")
+
+
+class Batch:
+    """Many independent instances advanced together on one GPU.
+
+    dists: list of (n_i, n_i) float32 distance matrices; ants: list of m_i
+    (default n_i); seeds: list of generator seeds (default 0..count-1).
+    Instance i evolves exactly as Colony(dists[i], ..., m_max=m_i).run(m_i, seeds[i], T).
+    """
+
+    def __init__(self, dists, alpha, beta, rho, Q=1.0, ants=None, seeds=None, *, tau0=1.0,
+                 elite_k=0, gamma_max=1.5, gamma_min=1.0, device="cuda", stream=None):
+        torch = _torch()
+        mats = [np.ascontiguousarray(d, dtype=np.float32) for d in dists]
+        self.count = len(mats)
+        self.ns = np.array([d.shape[0] for d in mats], dtype=np.int32)
+        self.ms = np.array(self.ns if ants is None else ants, dtype=np.int32)
+        self.seeds = np.array(range(self.count) if seeds is None else seeds, dtype=np.uint64)
+        offsets = np.zeros(self.count, dtype=np.int64)
+        offsets[1:] = np.cumsum((self.ns.astype(np.int64) ** 2))[:-1]
+        flat = np.concatenate([d.ravel() for d in mats])
+        dev_dists = torch.from_numpy(flat).to(device)
+        self.device = dev_dists.device
+        self._stream = stream
+        nbytes = lib().aco_batch_workspace_bytes(self.ns.ctypes.data_as(ctypes.c_void_p),
+                                                 self.ms.ctypes.data_as(ctypes.c_void_p),
+                                                 self.count)
+        if nbytes == 0:
+            raise ValueError("invalid batch sizes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        params = AcoParams(tau0, elite_k, gamma_max, gamma_min)
+        handle = ctypes.c_void_p()
+        self._b = None
+        check(lib().aco_batch_create(ctypes.c_void_p(dev_dists.data_ptr()),
+                                     offsets.ctypes.data_as(ctypes.c_void_p),
+                                     self.ns.ctypes.data_as(ctypes.c_void_p),
+                                     self.ms.ctypes.data_as(ctypes.c_void_p),
+                                     self.seeds.ctypes.data_as(ctypes.c_void_p), self.count,
+                                     alpha, beta, rho, Q, ctypes.byref(params),
+                                     ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     _stream_handle(stream), ctypes.byref(handle)),
+              "aco_batch_create")
+        self._b = handle
+
+    def close(self):
+        if self._b is not None:
+            lib().aco_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedules(self, table, persistent_waves=0):
+        """table: list of (n_max, schedule) pairs."""
+        arr = (ScheduleEntry * max(len(table), 1))(*[ScheduleEntry(a, b) for a, b in table])
+        check(lib().aco_batch_set_schedules(self._b, arr, len(table), persistent_waves),
+              "aco_batch_set_schedules")
+
+    def run(self, iters, use_graph=True):
+        check(lib().aco_batch_run(self._b, iters, 1 if use_graph else 0), "aco_batch_run")
+
+    def sync(self):
+        check(lib().aco_batch_sync(self._b), "aco_batch_sync")
+
+    def best(self):
+        lens = np.zeros(self.count, np.float32)
+        its = np.zeros(self.count, np.int32)
+        tours = np.zeros(int(self.ns.sum()), np.int32)
+        check(lib().aco_batch_best(self._b, lens.ctypes.data_as(ctypes.c_void_p),
+                                   its.ctypes.data_as(ctypes.c_void_p),
+                                   tours.ctypes.data_as(ctypes.c_void_p)), "aco_batch_best")
+        split = np.split(tours, np.cumsum(self.ns)[:-1])
+        return lens, its, split
+
+    def view(self, i):
+        v = BatchView()
+        check(lib().aco_batch_instance(self._b, i, ctypes.byref(v)), "aco_batch_instance")
+        return v
+
+    def _dev(self, ptr, dtype, shape):
+        torch = _torch()
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        count = int(np.prod(shape))
+        off = ptr - self.workspace.data_ptr()
+        assert 0 <= off and off + count * itemsize <= self.workspace.numel()
+        return self.workspace[off:off + count * itemsize].view(dtype).view(*shape)
+
+    def tau(self, i):
+        v = self.view(i)
+        return self._dev(v.tau, _torch().float32, (v.n, v.ld))[:, :v.n]
+
+    def P(self, i):
+        v = self.view(i)
+        return self._dev(v.P, _torch().float32, (v.n, v.ld))[:, :v.n]
+
+    def tours(self, i):
+        v = self.view(i)
+        return self._dev(v.tours, _torch().int32, (v.m, v.n))
+
+    def lengths(self, i):
+        v = self.view(i)
+        return self._dev(v.lengths, _torch().float32, (v.m,))

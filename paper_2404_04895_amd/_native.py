@@ -21,6 +21,20 @@ class AcoParams(ctypes.Structure):
                 ("gamma_max", ctypes.c_float), ("gamma_min", ctypes.c_float)]
 
 
+class ScheduleEntry(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+class BatchView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ld", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("deposit_scale", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("tau", ctypes.c_void_p), ("P", ctypes.c_void_p), ("tours", ctypes.c_void_p),
+                ("lengths", ctypes.c_void_p), ("best_tour", ctypes.c_void_p)]
+
+
+SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE = -1, 0, 1, 2, 3, 4
+SCHEDULES = (SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE)
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _u32 = ctypes.c_uint32
@@ -50,6 +64,16 @@ SIGNATURES = {
     "aco_get_state": (_i32, [_vp, _vp, ctypes.POINTER(_u32)]),
     "aco_set_state": (_i32, [_vp, _vp, _u32]),
     "aco_uniforms": (_i32, [_u64, _u32, _u32, _u32, _i32, _vp, _vp]),
+    "aco_set_schedule": (_i32, [_vp, _i32]),
+    "aco_batch_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, _i32]),
+    "aco_batch_create": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp, _vp,
+                                ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "aco_batch_set_schedules": (_i32, [_vp, _vp, _i32, _i32]),
+    "aco_batch_run": (_i32, [_vp, _i32, _i32]),
+    "aco_batch_best": (_i32, [_vp, _vp, _vp, _vp]),
+    "aco_batch_instance": (_i32, [_vp, _i32, ctypes.POINTER(BatchView)]),
+    "aco_batch_sync": (_i32, [_vp]),
+    "aco_batch_destroy": (None, [_vp]),
     "aco_sync": (_i32, [_vp]),
     "aco_destroy": (None, [_vp]),
     "aco_last_error": (ctypes.c_char_p, []),

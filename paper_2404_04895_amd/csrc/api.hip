@@ -8,7 +8,7 @@
 #include <new>
 
 #include "aco.h"
-#include "internal.hpp"
+#include "construct.hpp"
 
 struct aco_ctx {
     int32_t n = 0, ld = 0, m_max = 0;
@@ -27,43 +27,17 @@ struct aco_ctx {
     int32_t last_m = 0;
     uint32_t last_iter = 0;
     uint32_t iter = 0;         // running iteration counter used by aco_run
+    int32_t schedule = -1;     // construct schedule (ACO_SCHED_*), -1: by size
 };
 
 namespace {
 
 thread_local char g_error[512] = "";
 
-aco_status fail(aco_status st, const char* fmt, ...) {
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_error, sizeof(g_error), fmt, ap);
-    va_end(ap);
-    return st;
-}
-
-aco_status hip_fail(hipError_t e, const char* where) {
-    return fail(ACO_EDEVICE, "%s: %s", where, hipGetErrorString(e));
-}
-
-#define ACO_HIP(call, where)                        \
-    do {                                            \
-        hipError_t e_ = (call);                     \
-        if (e_ != hipSuccess) return hip_fail(e_, where); \
-    } while (0)
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-bool finite_positive(float x) { return isfinite(x) && x > 0.0f; }
-
-// Largest S with m_max * Q / L_lb * 2^S < 2^62 (no pheromone cell can then
-// overflow a signed 64-bit sum: a cell gets at most one weight per ant).
-int32_t quantisation_exponent(double lower_bound, int32_t m_max, float Q) {
-    const double x = static_cast<double>(m_max) * static_cast<double>(Q) / lower_bound;
-    int32_t S = static_cast<int32_t>(floor(62.0 - log2(x)));
-    while (ldexp(x, S) >= 0x1p62) --S;
-    while (ldexp(x, S + 1) < 0x1p62) ++S;
-    return S;
-}
+using aco::fail;
+using aco::hip_fail;
+using aco::align_up;
+using aco::finite_positive;
 
 aco_status check_ctx(const aco_ctx* ctx) {
     if (!ctx) return fail(ACO_EINVAL, "null context");
@@ -80,6 +54,41 @@ aco_status bind_device(const aco_ctx* ctx) {
 }  // namespace
 
 namespace aco {
+
+aco_status fail(aco_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof(g_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+aco_status hip_fail(hipError_t e, const char* where) {
+    return fail(ACO_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+void clear_error() { g_error[0] = '\0'; }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool finite_positive(float x) { return isfinite(x) && x > 0.0f; }
+
+int32_t quantisation_exponent(double lower_bound, int32_t m_max, float Q) {
+    const double x = static_cast<double>(m_max) * static_cast<double>(Q) / lower_bound;
+    int32_t S = static_cast<int32_t>(floor(62.0 - log2(x)));
+    while (ldexp(x, S) >= 0x1p62) --S;
+    while (ldexp(x, S + 1) < 0x1p62) ++S;
+    return S;
+}
+
+hipError_t launch_init_state(const float* dist_dense, int32_t n, int32_t ld, float tau0,
+                             const Buffers& B, hipStream_t stream) {
+    hipError_t e = launch_copy_padded(dist_dense, B.dist, n, ld, stream);
+    if (e != hipSuccess) return e;
+    e = launch_reset_tau(n, ld, tau0, B.tau, B.P, stream);
+    if (e != hipSuccess) return e;
+    return launch_clear_best(B.best, 1, stream);
+}
 
 Layout make_layout(int32_t n, int32_t ld, int32_t m_max) {
     Layout L{};
@@ -156,7 +165,7 @@ float aco_gamma_schedule(int32_t t, int32_t T, float gamma_max, float gamma_min)
 aco_status aco_create(const float* dist_dev, int32_t n, float alpha, float beta, float rho,
                       float Q, int32_t m_max, void* workspace_dev, size_t workspace_bytes,
                       void* hip_stream, aco_ctx** out) {
-    g_error[0] = '\0';
+    aco::clear_error();
     if (!out) return fail(ACO_EINVAL, "aco_create: out is NULL");
     *out = nullptr;
     if (!dist_dev) return fail(ACO_EINVAL, "aco_create: dist is NULL");
@@ -199,7 +208,8 @@ aco_status aco_create(const float* dist_dev, int32_t n, float alpha, float beta,
     if (e != hipSuccess) return bail(hip_fail(e, "hipGetDevice"));
     e = aco::prepare_kernels();
     if (e != hipSuccess) return bail(hip_fail(e, "prepare kernels"));
-    e = aco::launch_validate(dist_dev, n, true, true, ctx->buf, ctx->stream);
+    e = aco::launch_validate(dist_dev, n, true, ctx->buf.row_min, ctx->buf.lower_bound,
+                             ctx->buf.flags, ctx->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "validate dist"));
     uint32_t flags = 0;
     double lower = 0.0;
@@ -218,7 +228,7 @@ aco_status aco_create(const float* dist_dev, int32_t n, float alpha, float beta,
                          (flags & aco::kFlagDiagonal) ? "non-zero diagonal; " : ""));
     }
     ctx->length_lower_bound = lower;
-    ctx->S = quantisation_exponent(lower, m_max, Q);
+    ctx->S = aco::quantisation_exponent(lower, m_max, Q);
     e = aco::launch_init_state(dist_dev, n, ld, ctx->params.tau0, ctx->buf, ctx->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "init state"));
     *out = ctx;
@@ -241,8 +251,9 @@ aco_status aco_set_params(aco_ctx* ctx, const aco_params* p) {
         return fail(ACO_EINVAL, "aco_set_params: gamma <= 0");
     if (aco_status st = bind_device(ctx)) return st;
     ctx->params = *p;
-    ACO_HIP(aco::launch_reset_tau(ctx->n, ctx->ld, p->tau0, ctx->buf, ctx->stream), "reset tau");
-    ACO_HIP(aco::launch_clear_best(ctx->buf, ctx->stream), "clear best");
+    ACO_HIP(aco::launch_reset_tau(ctx->n, ctx->ld, p->tau0, ctx->buf.tau, ctx->buf.P, ctx->stream),
+            "reset tau");
+    ACO_HIP(aco::launch_clear_best(ctx->buf.best, 1, ctx->stream), "clear best");
     ctx->have_P = false;
     ctx->have_tours = false;
     return ACO_OK;
@@ -256,7 +267,8 @@ aco_status aco_set_eta(aco_ctx* ctx, const float* eta_dev) {
         ctx->eta_active = false;
         return ACO_OK;
     }
-    ACO_HIP(aco::launch_validate(eta_dev, ctx->n, false, false, ctx->buf, ctx->stream),
+    ACO_HIP(aco::launch_validate(eta_dev, ctx->n, false, nullptr, nullptr, ctx->buf.flags,
+                                 ctx->stream),
             "validate eta");
     uint32_t flags = 0;
     ACO_HIP(hipMemcpyAsync(&flags, ctx->buf.flags, sizeof(flags), hipMemcpyDeviceToHost,
@@ -275,6 +287,14 @@ aco_status aco_set_eta(aco_ctx* ctx, const float* eta_dev) {
 
 int32_t aco_eta_active(const aco_ctx* ctx) { return (ctx && ctx->eta_active) ? 1 : 0; }
 
+aco_status aco_set_schedule(aco_ctx* ctx, int32_t schedule) {
+    if (aco_status st = check_ctx(ctx)) return st;
+    if (schedule != ACO_SCHED_AUTO && !aco::schedule_valid(schedule))
+        return fail(ACO_EINVAL, "aco_set_schedule: unknown schedule %d", schedule);
+    ctx->schedule = schedule;
+    return ACO_OK;
+}
+
 aco_status aco_transition(aco_ctx* ctx, float gamma) {
     if (aco_status st = check_ctx(ctx)) return st;
     if (!finite_positive(gamma)) return fail(ACO_EINVAL, "aco_transition: gamma <= 0");
@@ -292,7 +312,8 @@ aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) 
         return fail(ACO_EINVAL, "aco_construct: m = %d outside [1, %d]", m, ctx->m_max);
     if (!ctx->have_P) return fail(ACO_ESTATE, "aco_construct: no transition matrix yet");
     if (aco_status st = bind_device(ctx)) return st;
-    ACO_HIP(aco::launch_construct(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, seed, iter,
+    const int32_t sched = ctx->schedule >= 0 ? ctx->schedule : aco::default_schedule(ctx->n);
+    ACO_HIP(aco::launch_construct(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, seed, iter, sched,
                                   ctx->stream),
             "construct");
     ctx->have_tours = true;
@@ -327,7 +348,7 @@ aco_status aco_run(aco_ctx* ctx, int32_t m, uint64_t seed, int32_t iters,
         return fail(ACO_EINVAL, "aco_run: m = %d outside [1, %d]", m, ctx->m_max);
     if (aco_status st = bind_device(ctx)) return st;
     const float gmax = ctx->params.gamma_max, gmin = ctx->params.gamma_min;
-    ACO_HIP(aco::launch_clear_best(ctx->buf, ctx->stream), "clear best");
+    ACO_HIP(aco::launch_clear_best(ctx->buf.best, 1, ctx->stream), "clear best");
     if (aco_status st = aco_transition(ctx, aco_gamma_schedule(0, iters, gmax, gmin))) return st;
     for (int32_t it = 0; it < iters; ++it) {
         if (aco_status st = aco_construct(ctx, m, seed, ctx->iter)) return st;

@@ -1,21 +1,26 @@
 // Tour construction by Adaptive Independent Roulette (Sec. 2.2, Sec. 2.4).
 //
-// One 64-lane wavefront per ant: the ants of Sec. 2.2's function mapping are
-// independent, so each gets its own wave and no wave ever waits on another.
-// At every step the wave streams the current city's row of P with one float4
-// per lane (coalesced, 1 KiB per wave-wide load), draws the four deviates of
-// that city block with one Philox call per lane, scores each unvisited city
-// by fl32(P[c,j] * r_j) and reduces the lane winners to the wave's argmax.
-// The visited set is a bitmask in LDS (one bit per city); cities at or past
-// n are pre-marked so the ragged last block needs no extra test.
+// An ant is a group of G lanes of one wavefront (G = 64: one ant per wave;
+// G = 32 or 16: two or four ants share a wave, for small instances).  The
+// ants of Sec. 2.2's function mapping are independent, so no group ever waits
+// on another.  At every step a group streams the current city's row of P as
+// one float4 per lane, draws the four deviates of each 4-city block with one
+// Philox call per lane, scores each unvisited city by fl32(P[c,j] * r_j) and
+// reduces the lane winners to the group's argmax.
+//
+// Per-group LDS: the visited bitmask (one bit per city; cities at or past n
+// are pre-set) and, when the live-block list is on, the sorted indices of the
+// 4-city blocks that still hold an unvisited city.  A block leaves the list
+// when its last city is taken, so a step scans only live blocks.  The
+// generator is keyed by block index, not list position or lane, so the group
+// width and the list change no result.
 //
 // Outputs per ant: the tour (m x n int32), its closed length (FP64 sum in
 // tour order, rounded once to FP32 -- the fitness f of Eq. (3)), and the
 // successor / predecessor of every city, stored city-major so that the
 // update kernel reads one contiguous row of each per city (Eq. (2)'s index
 // matrix, held as two maps).
-#include "internal.hpp"
-#include "philox.hpp"
+#include "construct.hpp"
 
 namespace aco {
 
@@ -36,64 +41,90 @@ __device__ __forceinline__ int32_t score_key(float p, uint32_t word, uint32_t ta
     return static_cast<int32_t>(__float_as_uint(score) | taken_sign);
 }
 
-// Cross-lane maximum of a wave (row shifts within each 16-lane row, then the
-// two row broadcasts); the result is read from lane 63.  Lanes without a
-// source keep their own value (max is idempotent).
-__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));  // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));  // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));  // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));  // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
+// All-reduce over the G lanes of a group (every lane gets the result):
+// quad butterflies, rotations by 4 and 8 within each 16-lane row, then the
+// permlane swaps that pair rows (G >= 32) and wave halves (G = 64).
+template <int G, bool IS_MAX>
+__device__ __forceinline__ int32_t group_reduce(int32_t v) {
+    auto op = [](int32_t a, int32_t b) { return IS_MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    if constexpr (G >= 32) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(v),
+                                                         static_cast<uint32_t>(v), false, false);
+        v = op(static_cast<int32_t>(sw[0]), static_cast<int32_t>(sw[1]));
+    }
+    if constexpr (G == 64) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(static_cast<uint32_t>(v),
+                                                         static_cast<uint32_t>(v), false, false);
+        v = op(static_cast<int32_t>(sw[0]), static_cast<int32_t>(sw[1]));
+    }
+    return v;
 }
 
-__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));
-    return __builtin_amdgcn_readlane(v, 63);
+template <int G>
+__device__ __forceinline__ int32_t group_sum(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    if constexpr (G >= 32) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(v),
+                                                         static_cast<uint32_t>(v), false, false);
+        v = static_cast<int32_t>(sw[0] + sw[1]);
+    }
+    if constexpr (G == 64) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(static_cast<uint32_t>(v),
+                                                         static_cast<uint32_t>(v), false, false);
+        v = static_cast<int32_t>(sw[0] + sw[1]);
+    }
+    return v;
 }
 
-// LDS layout per ant: the visited bitmask (one bit per city, cities >= n
-// pre-set) followed by the live-block list: the indices of the 4-city blocks
-// that still hold an unvisited city, in increasing order.  A block leaves the
-// list when its last city is taken, so a step scans only live blocks; the
-// generator is keyed by block index, not list position, so this changes no
-// result.
-__host__ __device__ constexpr int32_t mask_words(int32_t nblk) { return (nblk + 7) >> 3; }
+// The value is the same on every lane of the group; for G = 64 that makes it
+// wave-uniform, which lets the compiler keep it in a scalar register.
+template <int G>
+__device__ __forceinline__ int32_t group_uniform(int32_t v) {
+    if constexpr (G == 64) return __builtin_amdgcn_readfirstlane(v);
+    return v;
+}
 
-__global__ __launch_bounds__(kWave) void construct_kernel(
-    const float* __restrict__ P, const float* __restrict__ dist, int32_t n, int32_t ld,
-    int32_t m_max, uint32_t key0, uint32_t key1, uint32_t iter, int32_t* __restrict__ tours,
-    float* __restrict__ lengths, int32_t* __restrict__ succ, int32_t* __restrict__ pred) {
-    extern __shared__ uint32_t lds[];
-    const int32_t ant = blockIdx.x;
-    const int32_t lane = threadIdx.x;
-    const int32_t nblk = (n + 3) >> 2;  // 4-city blocks (one Philox call each)
+// Build the tours of up to 64/G ants of one instance: group g of this wave
+// builds ant ant0 + g if g < nants.  `lds` is this wave's LDS region of
+// (64/G) * group_lds_words(n, LIVE) words.
+template <int G, bool LIVE>
+__device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nants,
+                                uint32_t* __restrict__ lds) {
+    const int32_t lane = threadIdx.x & (kWave - 1);
+    const int32_t g = lane / G;
+    const int32_t gl = lane % G;
+    if (g >= nants) return;  // whole groups idle; no lane of an active group depends on them
+    const int32_t n = I.n;
+    const int32_t ant = ant0 + g;
+    const int32_t nblk = (n + 3) >> 2;
     const int32_t nwords = mask_words(nblk);
-    uint32_t* visited = lds;
-    uint16_t* live = reinterpret_cast<uint16_t*>(lds + nwords);
+    uint32_t* visited = lds + g * group_lds_words(n, LIVE);
+    uint16_t* live = reinterpret_cast<uint16_t*>(visited + nwords);
 
-    for (int32_t w = lane; w < nwords; w += kWave) {
+    for (int32_t w = gl; w < nwords; w += G) {
         const int32_t j0 = w * 32;
         uint32_t bits = 0u;
         if (j0 + 32 > n) bits = (j0 >= n) ? 0xFFFFFFFFu : (0xFFFFFFFFu << (n - j0));
         visited[w] = bits;
     }
-    for (int32_t i = lane; i < nblk; i += kWave) live[i] = static_cast<uint16_t>(i);
+    if constexpr (LIVE) {
+        for (int32_t i = gl; i < nblk; i += G) live[i] = static_cast<uint16_t>(i);
+    }
     int32_t nlive = nblk;
+    __builtin_amdgcn_wave_barrier();
 
     // Start city (Sec. 2.2 initialization): word 0 of counter (0, 0, ant, iter).
-    const PhiloxOut s0 = philox10(0u, 0u, static_cast<uint32_t>(ant), iter, key0, key1);
+    const PhiloxOut s0 = philox10(0u, 0u, static_cast<uint32_t>(ant), I.iter, I.key0, I.key1);
     const int32_t start = static_cast<int32_t>(__umulhi(s0.w0, static_cast<uint32_t>(n)));
-    __syncthreads();
 
-    int32_t* tour = tours + static_cast<size_t>(ant) * n;
+    int32_t* tour = I.tours + static_cast<size_t>(ant) * n;
     int32_t cur = start;
     int32_t next = start;
     double len = 0.0;
@@ -101,19 +132,19 @@ __global__ __launch_bounds__(kWave) void construct_kernel(
 
     for (int32_t s = 0; s < n; ++s) {
         if (s > 0) {
-            const float* row = P + static_cast<size_t>(cur) * ld;
+            const float* row = I.P + static_cast<size_t>(cur) * I.ld;
             int32_t best_key = -1;
             int32_t best_j = 0x7FFFFFFF;
-            const int32_t nchunk = (nlive + kWave - 1) >> 6;
-            for (int32_t k = 0; k < nchunk; ++k) {
-                const int32_t pos = (k << 6) + lane;
-                if (pos < nlive) {
-                    const int32_t b = live[pos];
+            const int32_t span = LIVE ? nlive : nblk;
+            for (int32_t base = 0; base < span; base += G) {
+                const int32_t pos = base + gl;
+                if (pos < span) {
+                    const int32_t b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
                     const float4 p = *reinterpret_cast<const float4*>(row + 4 * b);
                     const PhiloxOut r = philox10_block(static_cast<uint32_t>(b),
                                                        static_cast<uint32_t>(s),
-                                                       static_cast<uint32_t>(ant), iter, key0,
-                                                       key1);
+                                                       static_cast<uint32_t>(ant), I.iter,
+                                                       I.key0, I.key1);
                     const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
                     const int32_t k0 = score_key(p.x, r.w0, taken << 31);
                     const int32_t k1 = score_key(p.y, r.w1, (taken << 30) & 0x80000000u);
@@ -133,62 +164,60 @@ __global__ __launch_bounds__(kWave) void construct_kernel(
                     }
                 }
             }
-            // Wave argmax: the largest key, and among equal keys the smallest city.
-            const int32_t top = wave_max_i32(best_key);
-            const uint64_t holders = __ballot(best_key == top);
-            if (__popcll(holders) == 1) {
-                next = __builtin_amdgcn_readlane(best_j, __ffsll(static_cast<long long>(holders)) - 1);
-            } else {
-                next = wave_min_i32(best_key == top ? best_j : 0x7FFFFFFF);
-            }
+            // Group argmax: the largest key, and among equal keys the smallest city.
+            const int32_t top = group_reduce<G, true>(best_key);
+            next = group_uniform<G>(group_reduce<G, false>(best_key == top ? best_j : 0x7FFFFFFF));
         }
         // record the step: visited bit, tour entry, successor/predecessor maps
-        const int32_t nb = next >> 2;
         const int32_t word = next >> 5;
-        uint32_t bits = 0u;
-        if (lane == 0) {
-            bits = visited[word] | (1u << (next & 31));
+        const uint32_t bits = visited[word] | (1u << (next & 31));
+        __builtin_amdgcn_wave_barrier();
+        if (gl == 0) {
             visited[word] = bits;
             tour[s] = next;
             if (s > 0) {
-                succ[static_cast<size_t>(cur) * m_max + ant] = next;
-                pred[static_cast<size_t>(next) * m_max + ant] = cur;
+                I.succ[static_cast<size_t>(cur) * I.m_stride + ant] = next;
+                I.pred[static_cast<size_t>(next) * I.m_stride + ant] = cur;
             }
         }
-        bits = __builtin_amdgcn_readfirstlane(bits);
         len += static_cast<double>(edge);
-        if (s > 0) edge = dist[static_cast<size_t>(cur) * ld + next];
+        if (s > 0) edge = I.dist[static_cast<size_t>(cur) * I.ld + next];
         cur = next;
-        // drop the block from the live list once its last city is taken
-        if (((bits >> ((nb & 7) << 2)) & 0xFu) == 0xFu) {
-            int32_t at = 0;
-            for (int32_t base = 0; base < nlive; base += kWave) {
-                const int32_t i = base + lane;
-                const uint64_t hit = __ballot(i < nlive && live[i] == nb);
-                if (hit) {
-                    at = base + __ffsll(static_cast<long long>(hit)) - 1;
-                    break;
+        if constexpr (LIVE) {
+            // drop the block from the live list once its last city is taken
+            const int32_t nb = next >> 2;
+            if (((bits >> ((nb & 7) << 2)) & 0xFu) == 0xFu) {
+                int32_t below = 0;  // live blocks before nb = its position in the list
+                for (int32_t i = gl; i < nlive; i += G) below += (live[i] < nb) ? 1 : 0;
+                const int32_t at = group_uniform<G>(group_sum<G>(below));
+                for (int32_t base = at; base < nlive - 1; base += G) {
+                    const int32_t i = base + gl;
+                    uint16_t v = 0;
+                    if (i < nlive - 1) v = live[i + 1];
+                    __builtin_amdgcn_wave_barrier();
+                    if (i < nlive - 1) live[i] = v;
+                    __builtin_amdgcn_wave_barrier();
                 }
+                --nlive;
             }
-            for (int32_t base = at; base < nlive - 1; base += kWave) {
-                const int32_t i = base + lane;
-                uint16_t v = 0;
-                if (i < nlive - 1) v = live[i + 1];
-                __builtin_amdgcn_wave_barrier();
-                if (i < nlive - 1) live[i] = v;
-                __builtin_amdgcn_wave_barrier();
-            }
-            --nlive;
         }
         __builtin_amdgcn_wave_barrier();
     }
     len += static_cast<double>(edge);
-    if (lane == 0) {
-        succ[static_cast<size_t>(cur) * m_max + ant] = start;
-        pred[static_cast<size_t>(start) * m_max + ant] = cur;
-        len += static_cast<double>(dist[static_cast<size_t>(cur) * ld + start]);
-        lengths[ant] = static_cast<float>(len);
+    if (gl == 0) {
+        I.succ[static_cast<size_t>(cur) * I.m_stride + ant] = start;
+        I.pred[static_cast<size_t>(start) * I.m_stride + ant] = cur;
+        len += static_cast<double>(I.dist[static_cast<size_t>(cur) * I.ld + start]);
+        I.lengths[ant] = static_cast<float>(len);
     }
+}
+
+template <int G, bool LIVE>
+__global__ __launch_bounds__(kWave) void construct_kernel(InstanceView I, int32_t m) {
+    extern __shared__ uint32_t lds[];
+    constexpr int32_t kGroups = kWave / G;
+    const int32_t ant0 = static_cast<int32_t>(blockIdx.x) * kGroups;
+    construct_group<G, LIVE>(I, ant0, min(kGroups, m - ant0), lds);
 }
 
 __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uint32_t ant,
@@ -200,16 +229,126 @@ __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uin
     out[j] = unit_from_word(words[j & 3]);
 }
 
+template <int G, bool LIVE>
+hipError_t launch_one(const InstanceView& I, int32_t m, hipStream_t stream) {
+    constexpr int32_t kGroups = kWave / G;
+    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(kGroups) *
+                       static_cast<size_t>(group_lds_words(I.n, LIVE));
+    hipLaunchKernelGGL((construct_kernel<G, LIVE>), dim3((m + kGroups - 1) / kGroups),
+                       dim3(kWave), lds, stream, I, m);
+    return hipGetLastError();
+}
+
+// ---- persistent construct over a batch of instances -----------------------
+
+template <int G, bool LIVE>
+__device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchPools& pools,
+                                         uint32_t iter, int32_t ant0, int32_t nants,
+                                         uint32_t* lds) {
+    InstanceView I;
+    I.P = pools.P + inst.off_mat;
+    I.dist = pools.dist + inst.off_mat;
+    I.n = inst.n;
+    I.ld = inst.ld;
+    I.tours = pools.tours + inst.off_tours;
+    I.lengths = pools.lengths + inst.off_ants;
+    I.succ = pools.succ + inst.off_succ;
+    I.pred = pools.pred + inst.off_succ;
+    I.m_stride = inst.m;
+    I.key0 = inst.key0;
+    I.key1 = inst.key1;
+    I.iter = iter;
+    construct_group<G, LIVE>(I, ant0, nants, lds);
+}
+
+// Each wave repeatedly takes the next task (instance, first ant, ant count,
+// schedule) from a queue ordered largest instance first, until the queue is
+// empty.  Every wave reaches the exit: the queue is finite and each task is
+// bounded by its instance size.
+__global__ __launch_bounds__(kWave) void batch_construct_kernel(
+    const BatchInstance* __restrict__ insts, const BatchTask* __restrict__ tasks, int32_t ntasks,
+    uint32_t* __restrict__ queue, const IterState* __restrict__ state, BatchPools pools) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t iter = state->iter;
+    for (;;) {
+        uint32_t t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= static_cast<uint32_t>(ntasks)) break;
+        const BatchTask task = tasks[t];
+        const BatchInstance inst = insts[task.instance];
+        switch (task.schedule) {
+            case kSched16: run_task<16, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+            case kSched32: run_task<32, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+            case kSched32Live: run_task<32, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
+            case kSched64: run_task<64, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+            default: run_task<64, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
-hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
-                            uint64_t seed, uint32_t iter, hipStream_t stream) {
+int32_t schedule_lanes(int32_t sched) {
+    switch (sched) {
+        case kSched16: return 16;
+        case kSched32:
+        case kSched32Live: return 32;
+        default: return 64;
+    }
+}
+
+bool schedule_live(int32_t sched) { return sched == kSched32Live || sched == kSched64Live; }
+
+bool schedule_valid(int32_t sched) { return sched >= kSched16 && sched <= kSched64Live; }
+
+int32_t default_schedule(int32_t n) {
     const int32_t nblk = (n + 3) >> 2;
-    const size_t lds = sizeof(uint32_t) * static_cast<size_t>(mask_words(nblk)) +
-                       sizeof(uint16_t) * static_cast<size_t>(nblk + 1);
-    hipLaunchKernelGGL(construct_kernel, dim3(m), dim3(kWave), lds, stream, B.P, B.dist, n, ld,
-                       m_max, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32),
-                       iter, B.tours, B.lengths, B.succ, B.pred);
+    if (nblk <= 16) return kSched16;
+    if (nblk <= 32) return kSched32;
+    if (nblk <= 64) return kSched64;
+    return kSched64Live;
+}
+
+size_t wave_lds_bytes(int32_t n, int32_t sched) {
+    return sizeof(uint32_t) * static_cast<size_t>(kWave / schedule_lanes(sched)) *
+           static_cast<size_t>(group_lds_words(n, schedule_live(sched)));
+}
+
+hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched,
+                                 hipStream_t stream) {
+    switch (sched) {
+        case kSched16: return launch_one<16, false>(I, m, stream);
+        case kSched32: return launch_one<32, false>(I, m, stream);
+        case kSched32Live: return launch_one<32, true>(I, m, stream);
+        case kSched64: return launch_one<64, false>(I, m, stream);
+        default: return launch_one<64, true>(I, m, stream);
+    }
+}
+
+hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
+                            uint64_t seed, uint32_t iter, int32_t sched, hipStream_t stream) {
+    InstanceView I;
+    I.P = B.P;
+    I.dist = B.dist;
+    I.n = n;
+    I.ld = ld;
+    I.tours = B.tours;
+    I.lengths = B.lengths;
+    I.succ = B.succ;
+    I.pred = B.pred;
+    I.m_stride = m_max;
+    I.key0 = static_cast<uint32_t>(seed);
+    I.key1 = static_cast<uint32_t>(seed >> 32);
+    I.iter = iter;
+    return launch_construct_view(I, m, sched, stream);
+}
+
+hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
+                                  int32_t grid, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_construct_kernel, dim3(grid), dim3(kWave), lds_bytes, stream,
+                       BD.insts, BD.tasks, ntasks, BD.queue, BD.state, BD.pools);
     return hipGetLastError();
 }
 

@@ -1,0 +1,112 @@
+// Descriptors shared by the construct kernels, the batched engine and the C ABI.
+#pragma once
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace aco {
+
+// One instance as the construct code sees it (single instance or one member
+// of a batch).
+struct InstanceView {
+    const float* P;      // n x ld transition matrix
+    const float* dist;   // n x ld distances
+    int32_t n, ld;
+    int32_t* tours;      // ants x n
+    float* lengths;      // ants
+    int32_t* succ;       // n x m_stride
+    int32_t* pred;       // n x m_stride
+    int32_t m_stride;
+    uint32_t key0, key1, iter;
+};
+
+// Construct schedules: lanes per ant and whether the live-block list is kept.
+// The numeric codes are the ACO_SCHED_* values of the C ABI.
+enum : int32_t {
+    kSched16 = 0,      // 16 lanes per ant, 4 ants per wave
+    kSched32 = 1,      // 32 lanes per ant, 2 ants per wave
+    kSched32Live = 2,  // 32 lanes per ant, live-block list
+    kSched64 = 3,      // one ant per wave
+    kSched64Live = 4,  // one ant per wave, live-block list
+};
+
+__host__ __device__ constexpr int32_t mask_words(int32_t nblk) { return (nblk + 7) >> 3; }
+
+// LDS words one ant needs: visited bitmask, then (optionally) the u16 list of
+// live blocks, rounded up to whole words.
+__host__ __device__ constexpr int32_t group_lds_words(int32_t n, bool live) {
+    return mask_words((n + 3) >> 2) + (live ? (((n + 3) >> 2) + 1) / 2 : 0);
+}
+
+int32_t schedule_lanes(int32_t sched);
+bool schedule_live(int32_t sched);
+bool schedule_valid(int32_t sched);
+int32_t default_schedule(int32_t n);
+size_t wave_lds_bytes(int32_t n, int32_t sched);
+
+// ---- batched engine --------------------------------------------------------
+struct BatchInstance {
+    int32_t n, ld, m, elite_k;
+    int64_t off_mat;     // element offset into the dist / tau / P / eta pools (n x ld)
+    int64_t off_tours;   // into the tours pool (m x n)
+    int64_t off_succ;    // into the succ / pred pools (n x m)
+    int64_t off_ants;    // into the lengths / weights pools (m)
+    int64_t off_cities;  // into the best-tour pool (n)
+    uint32_t key0, key1;
+    int32_t S;           // deposit quantisation exponent
+    float pad;
+};
+
+struct BatchTask {
+    int32_t instance, ant0, nants, schedule;
+};
+
+struct RowTask {
+    int32_t instance, row;
+};
+
+// Iteration counters read by the kernels of a captured iteration and
+// advanced on the device by its last kernel.
+struct IterState {
+    uint32_t iter;        // generator iteration word of the current iteration
+    int32_t t;            // index into the run's gamma schedule
+    int32_t T;            // iterations in the run
+    float gamma_next;     // gamma for the P built at the end of this iteration
+};
+
+struct BatchPools {
+    float* dist;
+    float* tau;
+    float* P;
+    int32_t* tours;
+    float* lengths;
+    int32_t* succ;
+    int32_t* pred;
+    int64_t* weight;
+    int32_t* best_tour;
+    BestRecord* best;
+};
+
+struct BatchDevice {
+    BatchInstance* insts;
+    BatchTask* tasks;
+    RowTask* rows;
+    uint32_t* queue;
+    IterState* state;
+    float* gammas;  // T + 1 entries
+    BatchPools pools;
+};
+
+hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched,
+                                 hipStream_t stream);
+hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
+                                  int32_t grid, hipStream_t stream);
+hipError_t launch_batch_rows(const BatchDevice& BD, int32_t nrows, int32_t max_ld,
+                             const float* gamma_ptr, bool apply_deposit, float alpha, float beta,
+                             float rho, hipStream_t stream);
+hipError_t launch_batch_ants(const BatchDevice& BD, int32_t count, float Q, hipStream_t stream);
+hipError_t launch_batch_advance(const BatchDevice& BD, hipStream_t stream);
+hipError_t launch_batch_arm(const BatchDevice& BD, uint32_t iter0, int32_t T,
+                            hipStream_t stream);
+
+}  // namespace aco

@@ -57,24 +57,41 @@ enum : uint32_t {
 // ---- launchers (each enqueues on `stream`, returns the launch status) ----
 hipError_t launch_init_state(const float* dist_dense, int32_t n, int32_t ld, float tau0,
                              const Buffers& B, hipStream_t stream);
-hipError_t launch_reset_tau(int32_t n, int32_t ld, float tau0, const Buffers& B,
+hipError_t launch_reset_tau(int32_t n, int32_t ld, float tau0, float* tau, float* P,
                             hipStream_t stream);
-hipError_t launch_validate(const float* mat_dense, int32_t n, bool check_symmetry,
-                           bool want_row_min, const Buffers& B, hipStream_t stream);
+hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, float* row_min,
+                           double* lower_bound, uint32_t* flags, hipStream_t stream);
 hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,
                               hipStream_t stream);
 hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
-                            uint64_t seed, uint32_t iter, hipStream_t stream);
+                            uint64_t seed, uint32_t iter, int32_t sched, hipStream_t stream);
 hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, float Q,
                                   int32_t S, hipStream_t stream);
 hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
                        hipStream_t stream);
-hipError_t launch_clear_best(const Buffers& B, hipStream_t stream);
+hipError_t launch_clear_best(BestRecord* best, int32_t count, hipStream_t stream);
 hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
                        bool apply_deposit, bool use_eta, float alpha, float beta, float rho,
                        int32_t S, float gamma, hipStream_t stream);
 hipError_t launch_uniforms(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
                            int32_t count, float* out, hipStream_t stream);
 hipError_t prepare_kernels();
+
+// Error reporting shared by the C ABI files (thread-local message).
+aco_status fail(aco_status st, const char* fmt, ...);
+aco_status hip_fail(hipError_t e, const char* where);
+void clear_error();
+size_t align_up(size_t x, size_t a);
+bool finite_positive(float x);
+
+#define ACO_HIP(call, where)                                       \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) return ::aco::hip_fail(e_, where);   \
+    } while (0)
+
+// Largest S with m_max * Q / L_lb * 2^S < 2^62 (no pheromone cell can then
+// overflow a signed 64-bit sum: a cell gets at most one weight per ant).
+int32_t quantisation_exponent(double lower_bound, int32_t m_max, float Q);
 
 }  // namespace aco

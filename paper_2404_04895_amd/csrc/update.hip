@@ -1,8 +1,8 @@
 // Pheromone update and transition matrix (Sec. 2.1 Eq. (1), Sec. 2.3 Eq. (2)-(3)),
 // plus the small per-iteration and set-up kernels around them.
 //
-// The row kernel is the only O(n^2) pass per iteration.  One workgroup owns
-// one row i of tau and P:
+// The row update is the only O(n^2) pass per iteration.  T threads own one
+// row i of tau and P (T = 256 for one instance, one wave per row in a batch):
 //   1. index-mapped deposit: for every ant, add its quantised weight at
 //      columns succ_a(i) and pred_a(i) of an int64 row accumulator in LDS
 //      (both orientations of every tour edge through i, i.e. row i of Eq. (3)'s
@@ -15,14 +15,13 @@
 // HBM traffic per element: tau read+write, dist (or eta) read, P write.
 #include <math.h>
 
-#include "internal.hpp"
+#include "construct.hpp"
 
 namespace aco {
 
 namespace {
 
 constexpr int kRowThreads = 256;
-constexpr int kRowWaves = kRowThreads / 64;
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -42,84 +41,153 @@ __device__ __forceinline__ float wave_minf(float v) {
     return v;
 }
 
+template <int T>
+__device__ __forceinline__ void sync_row() {
+    if constexpr (T > 64) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Row maximum across the T threads; every thread gets the result (exact in
+// any order).
+template <int T>
+__device__ __forceinline__ double row_max_all(double v, double* red) {
+    v = wave_max(v);
+    if constexpr (T > 64) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[wave] = v;
+        __syncthreads();
+        double r = red[0];
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w) r = fmax(r, red[w]);
+        __syncthreads();
+        return r;
+    }
+    return v;
+}
+
+// Sum over j of f(j) for j < n with a fixed association, whatever T is: each
+// 64-column chunk is summed by a 64-lane butterfly (every lane gets the same
+// bits: IEEE addition is commutative), then the chunk sums are added in chunk
+// order starting from +0.  One instance and a batch therefore build
+// bit-identical rows.
+template <int T, typename F>
+__device__ __forceinline__ double row_sum_fixed(int32_t n, F f, double* partial) {
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t wave = (threadIdx.x & (T - 1)) >> 6;
+    const int32_t nchunks = (n + 63) >> 6;
+    double total = 0.0;
+    for (int32_t c = wave; c < nchunks; c += T / 64) {
+        const int32_t j = (c << 6) + lane;
+        const double chunk = wave_sum(j < n ? f(j) : 0.0);
+        if constexpr (T == 64) {
+            total += chunk;
+        } else {
+            if (lane == 0) partial[c] = chunk;
+        }
+    }
+    if constexpr (T > 64) {
+        __syncthreads();
+        for (int32_t c = 0; c < nchunks; ++c) total += partial[c];
+        __syncthreads();
+    }
+    return total;
+}
+
+struct RowArgs {
+    float* tau;             // row i of tau
+    float* P;               // row i of P
+    const float* dist;      // row i of dist
+    const float* eta;       // row i of eta, or null for 1/d
+    const int32_t* succ;    // row i of succ (m entries)
+    const int32_t* pred;    // row i of pred
+    const int64_t* weight;  // m quantised ant weights
+    int32_t n, ld, i, m;
+    int32_t apply_deposit;
+    double keep, unit, alpha, beta, gamma;
+};
+
+template <int T>
+__device__ void update_row(const RowArgs& a, double* lnw, double* red) {
+    const int32_t tid = threadIdx.x & (T - 1);
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lnw);
+    if (a.apply_deposit) {
+        for (int32_t j = tid; j < a.n; j += T) acc[j] = 0ull;
+        sync_row<T>();
+        for (int32_t k = tid; k < a.m; k += T) {
+            const int64_t q = a.weight[k];
+            if (q != 0) {
+                atomicAdd(&acc[a.succ[k]], static_cast<unsigned long long>(q));
+                atomicAdd(&acc[a.pred[k]], static_cast<unsigned long long>(q));
+            }
+        }
+        sync_row<T>();
+    }
+    double local_max = -INFINITY;
+    for (int32_t j = tid; j < a.n; j += T) {
+        if (j == a.i) continue;
+        float t = a.tau[j];
+        if (a.apply_deposit) {
+            const double add = static_cast<double>(static_cast<int64_t>(acc[j])) * a.unit;
+            t = static_cast<float>(__fma_rn(a.keep, static_cast<double>(t), add));
+            a.tau[j] = t;
+        }
+        const double ln_eta = a.eta ? log(static_cast<double>(a.eta[j]))
+                                    : -log(static_cast<double>(a.dist[j]));
+        const double w = a.alpha * log(static_cast<double>(t)) + a.beta * ln_eta;
+        lnw[j] = w;
+        local_max = fmax(local_max, w);
+    }
+    const double row_max = row_max_all<T>(local_max, red);
+    sync_row<T>();
+    const double total = row_sum_fixed<T>(
+        a.n, [&](int32_t j) { return j == a.i ? 0.0 : exp(lnw[j] - row_max); }, red);
+    const double ln_total = row_max + log(total);
+    for (int32_t j = tid; j < a.ld; j += T) {
+        float p = 0.0f;
+        if (j < a.n && j != a.i) p = static_cast<float>(exp((lnw[j] - ln_total) / a.gamma));
+        a.P[j] = p;
+    }
+}
+
 __global__ __launch_bounds__(kRowThreads) void row_kernel(
     float* __restrict__ tau, float* __restrict__ P, const float* __restrict__ dist,
     const float* __restrict__ eta, int32_t n, int32_t ld, int32_t m, int32_t m_max,
     const int32_t* __restrict__ succ, const int32_t* __restrict__ pred,
     const int64_t* __restrict__ weight, int32_t apply_deposit, double keep, double unit,
     double alpha, double beta, double gamma) {
-    extern __shared__ double lnw[];  // ld entries; first holds the int64 deposit row
-    __shared__ double red[kRowWaves];
+    extern __shared__ double lnw[];
+    __shared__ double red[ACO_LDS_ROW_MAX / 64];  // wave maxima, then chunk sums
     const int32_t i = blockIdx.x;
-    const int32_t tid = threadIdx.x;
-    const int32_t lane = tid & 63;
-    const int32_t wave = tid >> 6;
-    const size_t row_off = static_cast<size_t>(i) * ld;
-    unsigned long long* acc = reinterpret_cast<unsigned long long*>(lnw);
-
-    if (apply_deposit) {
-        for (int32_t j = tid; j < n; j += kRowThreads) acc[j] = 0ull;
-        __syncthreads();
-        const int32_t* srow = succ + static_cast<size_t>(i) * m_max;
-        const int32_t* prow = pred + static_cast<size_t>(i) * m_max;
-        for (int32_t a = tid; a < m; a += kRowThreads) {
-            const int64_t q = weight[a];
-            if (q != 0) {
-                atomicAdd(&acc[srow[a]], static_cast<unsigned long long>(q));
-                atomicAdd(&acc[prow[a]], static_cast<unsigned long long>(q));
-            }
-        }
-        __syncthreads();
-    }
-
-    double local_max = -INFINITY;
-    for (int32_t j = tid; j < n; j += kRowThreads) {
-        if (j == i) continue;
-        float t = tau[row_off + j];
-        if (apply_deposit) {
-            const double add = static_cast<double>(static_cast<int64_t>(acc[j])) * unit;
-            t = static_cast<float>(__fma_rn(keep, static_cast<double>(t), add));
-            tau[row_off + j] = t;
-        }
-        const double ln_eta = eta ? log(static_cast<double>(eta[row_off + j]))
-                                  : -log(static_cast<double>(dist[row_off + j]));
-        const double w = alpha * log(static_cast<double>(t)) + beta * ln_eta;
-        lnw[j] = w;
-        local_max = fmax(local_max, w);
-    }
-    local_max = wave_max(local_max);
-    if (lane == 0) red[wave] = local_max;
-    __syncthreads();
-    double row_max = red[0];
-#pragma unroll
-    for (int w = 1; w < kRowWaves; ++w) row_max = fmax(row_max, red[w]);
-    __syncthreads();
-
-    double local_sum = 0.0;
-    for (int32_t j = tid; j < n; j += kRowThreads) {
-        if (j != i) local_sum += exp(lnw[j] - row_max);
-    }
-    local_sum = wave_sum(local_sum);
-    if (lane == 0) red[wave] = local_sum;
-    __syncthreads();
-    double total = red[0];
-#pragma unroll
-    for (int w = 1; w < kRowWaves; ++w) total += red[w];
-    const double ln_total = row_max + log(total);
-
-    for (int32_t j = tid; j < ld; j += kRowThreads) {
-        float p = 0.0f;
-        if (j < n && j != i) p = static_cast<float>(exp((lnw[j] - ln_total) / gamma));
-        P[row_off + j] = p;
-    }
+    const size_t off = static_cast<size_t>(i) * ld;
+    RowArgs a;
+    a.tau = tau + off;
+    a.P = P + off;
+    a.dist = dist + off;
+    a.eta = eta ? eta + off : nullptr;
+    a.succ = succ + static_cast<size_t>(i) * m_max;
+    a.pred = pred + static_cast<size_t>(i) * m_max;
+    a.weight = weight;
+    a.n = n;
+    a.ld = ld;
+    a.i = i;
+    a.m = m;
+    a.apply_deposit = apply_deposit;
+    a.keep = keep;
+    a.unit = unit;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = gamma;
+    update_row<kRowThreads>(a, lnw, red);
 }
 
 // Quantised deposit weight of each ant: round(Q / L_a * 2^S) if the ant is in
 // the elite set (the elite_k shortest by (length, index)), else 0.
-__global__ void weights_kernel(const float* __restrict__ lengths, int32_t m, int32_t elite_k,
-                               double Q, double scale, int64_t* __restrict__ weight) {
-    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m) return;
+__device__ __forceinline__ int64_t ant_weight(const float* lengths, int32_t a, int32_t m,
+                                              int32_t elite_k, double Q, double scale) {
     const float La = lengths[a];
     bool elite = true;
     if (elite_k > 0 && elite_k < m) {
@@ -130,23 +198,29 @@ __global__ void weights_kernel(const float* __restrict__ lengths, int32_t m, int
         }
         elite = rank < elite_k;
     }
-    weight[a] = elite ? __double2ll_rn((Q / static_cast<double>(La)) * scale) : 0;
+    return elite ? __double2ll_rn((Q / static_cast<double>(La)) * scale) : 0;
 }
 
-// Best-so-far: shortest tour of this iteration (ties to the smaller ant)
-// replaces the record only if strictly shorter.
-__global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ lengths,
-                                                    const int32_t* __restrict__ tours, int32_t n,
-                                                    int32_t m, uint32_t iter,
-                                                    BestRecord* __restrict__ best,
-                                                    int32_t* __restrict__ best_tour) {
-    __shared__ float red_len[16];
-    __shared__ int32_t red_ant[16];
+__global__ void weights_kernel(const float* __restrict__ lengths, int32_t m, int32_t elite_k,
+                               double Q, double scale, int64_t* __restrict__ weight) {
+    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= m) return;
+    weight[a] = ant_weight(lengths, a, m, elite_k, Q, scale);
+}
+
+// Best-so-far: the shortest tour of this iteration (ties to the smaller ant)
+// replaces the record only if strictly shorter.  T threads, one record.
+template <int T>
+__device__ void best_update(const float* __restrict__ lengths, const int32_t* __restrict__ tours,
+                            int32_t n, int32_t m, uint32_t iter, BestRecord* __restrict__ best,
+                            int32_t* __restrict__ best_tour) {
+    __shared__ float red_len[T / 64];
+    __shared__ int32_t red_ant[T / 64];
     __shared__ int32_t winner;
     const int32_t tid = threadIdx.x;
     float bl = INFINITY;
     int32_t ba = 0x7FFFFFFF;
-    for (int32_t a = tid; a < m; a += blockDim.x) {
+    for (int32_t a = tid; a < m; a += T) {
         const float L = lengths[a];
         if (L < bl || (L == bl && a < ba)) {
             bl = L;
@@ -168,8 +242,7 @@ __global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ le
     }
     __syncthreads();
     if (tid == 0) {
-        const int waves = (blockDim.x + 63) >> 6;
-        for (int w = 1; w < waves; ++w) {
+        for (int w = 1; w < T / 64; ++w) {
             if (red_len[w] < bl || (red_len[w] == bl && red_ant[w] < ba)) {
                 bl = red_len[w];
                 ba = red_ant[w];
@@ -186,15 +259,25 @@ __global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ le
     const int32_t w = winner;
     if (w >= 0) {
         const int32_t* src = tours + static_cast<size_t>(w) * n;
-        for (int32_t s = tid; s < n; s += blockDim.x) best_tour[s] = src[s];
+        for (int32_t s = tid; s < n; s += T) best_tour[s] = src[s];
     }
 }
 
-__global__ void clear_best_kernel(BestRecord* best) {
-    best->len = INFINITY;
-    best->iter = -1;
-    best->ant = -1;
-    best->pad = 0;
+__global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ lengths,
+                                                    const int32_t* __restrict__ tours, int32_t n,
+                                                    int32_t m, uint32_t iter,
+                                                    BestRecord* __restrict__ best,
+                                                    int32_t* __restrict__ best_tour) {
+    best_update<1024>(lengths, tours, n, m, iter, best, best_tour);
+}
+
+__global__ void clear_best_kernel(BestRecord* best, int32_t count) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    best[k].len = INFINITY;
+    best[k].iter = -1;
+    best[k].ant = -1;
+    best[k].pad = 0;
 }
 
 // Copy a dense n x n matrix into the padded n x ld layout (zero padding).
@@ -213,6 +296,10 @@ __global__ void reset_tau_kernel(float* __restrict__ tau, float* __restrict__ P,
         tau[ij] = (j < n && j != i) ? tau0 : 0.0f;
         P[ij] = 0.0f;
     }
+}
+
+__global__ void clear_flags_kernel(uint32_t* flags) {
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0u;
 }
 
 // Input check, one workgroup per row: finite, > 0 off the diagonal, zero on
@@ -262,10 +349,87 @@ __global__ void lower_bound_kernel(const float* __restrict__ row_min, int32_t n,
     *out = total;
 }
 
+// ---- batched engine kernels -------------------------------------------------
+
+// One wave per (instance, row).
+__global__ __launch_bounds__(64) void batch_rows_kernel(const BatchInstance* __restrict__ insts,
+                                                        const RowTask* __restrict__ rows,
+                                                        int32_t nrows, BatchPools pools,
+                                                        const float* __restrict__ gamma_ptr,
+                                                        int32_t apply_deposit, double keep,
+                                                        double alpha, double beta) {
+    extern __shared__ double lnw[];
+    const int32_t r = blockIdx.x;
+    if (r >= nrows) return;
+    const RowTask rt = rows[r];
+    const BatchInstance in = insts[rt.instance];
+    const size_t off = static_cast<size_t>(in.off_mat) + static_cast<size_t>(rt.row) * in.ld;
+    RowArgs a;
+    a.tau = pools.tau + off;
+    a.P = pools.P + off;
+    a.dist = pools.dist + off;
+    a.eta = nullptr;
+    a.succ = pools.succ + in.off_succ + static_cast<size_t>(rt.row) * in.m;
+    a.pred = pools.pred + in.off_succ + static_cast<size_t>(rt.row) * in.m;
+    a.weight = pools.weight + in.off_ants;
+    a.n = in.n;
+    a.ld = in.ld;
+    a.i = rt.row;
+    a.m = in.m;
+    a.apply_deposit = apply_deposit;
+    a.keep = keep;
+    a.unit = ldexp(1.0, -in.S);
+    a.alpha = alpha;
+    a.beta = beta;
+    a.gamma = static_cast<double>(*gamma_ptr);
+    update_row<64>(a, lnw, nullptr);
+}
+
+// One workgroup per instance: best-so-far record, then the ants' weights.
+__global__ __launch_bounds__(256) void batch_ants_kernel(const BatchInstance* __restrict__ insts,
+                                                         BatchPools pools,
+                                                         const IterState* __restrict__ state,
+                                                         double Q) {
+    const BatchInstance in = insts[blockIdx.x];
+    const float* lengths = pools.lengths + in.off_ants;
+    best_update<256>(lengths, pools.tours + in.off_tours, in.n, in.m, state->iter,
+                     pools.best + blockIdx.x, pools.best_tour + in.off_cities);
+    const double scale = ldexp(1.0, in.S);
+    for (int32_t a = threadIdx.x; a < in.m; a += 256)
+        pools.weight[in.off_ants + a] = ant_weight(lengths, a, in.m, in.elite_k, Q, scale);
+}
+
+// Last kernel of an iteration: advance the counters and re-arm the queue.
+__global__ void batch_advance_kernel(IterState* __restrict__ state,
+                                     const float* __restrict__ gammas,
+                                     uint32_t* __restrict__ queue) {
+    IterState s = *state;
+    s.iter += 1u;
+    s.t += 1;
+    s.gamma_next = gammas[min(s.t + 1, s.T)];
+    *state = s;
+    *queue = 0u;
+}
+
+__global__ void batch_arm_kernel(IterState* __restrict__ state, const float* __restrict__ gammas,
+                                 uint32_t* __restrict__ queue, uint32_t iter0, int32_t T) {
+    IterState s;
+    s.iter = iter0;
+    s.t = 0;
+    s.T = T;
+    s.gamma_next = gammas[min(1, T)];
+    *state = s;
+    *queue = 0u;
+}
+
 }  // namespace
 
 hipError_t prepare_kernels() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(row_kernel),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(row_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(sizeof(double) * ACO_LDS_ROW_MAX));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(batch_rows_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                static_cast<int>(sizeof(double) * ACO_LDS_ROW_MAX));
 }
@@ -277,38 +441,29 @@ hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int
     return hipGetLastError();
 }
 
-hipError_t launch_reset_tau(int32_t n, int32_t ld, float tau0, const Buffers& B,
+hipError_t launch_reset_tau(int32_t n, int32_t ld, float tau0, float* tau, float* P,
                             hipStream_t stream) {
-    hipLaunchKernelGGL(reset_tau_kernel, dim3((ld + 255) / 256, n), dim3(256), 0, stream, B.tau,
-                       B.P, n, ld, tau0);
+    hipLaunchKernelGGL(reset_tau_kernel, dim3((ld + 255) / 256, n), dim3(256), 0, stream, tau, P,
+                       n, ld, tau0);
     return hipGetLastError();
 }
 
-hipError_t launch_clear_best(const Buffers& B, hipStream_t stream) {
-    hipLaunchKernelGGL(clear_best_kernel, dim3(1), dim3(1), 0, stream, B.best);
+hipError_t launch_clear_best(BestRecord* best, int32_t count, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_best_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, best,
+                       count);
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(const float* dist_dense, int32_t n, int32_t ld, float tau0,
-                             const Buffers& B, hipStream_t stream) {
-    hipError_t e = launch_copy_padded(dist_dense, B.dist, n, ld, stream);
-    if (e != hipSuccess) return e;
-    e = launch_reset_tau(n, ld, tau0, B, stream);
-    if (e != hipSuccess) return e;
-    return launch_clear_best(B, stream);
-}
-
-hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance,
-                           bool want_row_min, const Buffers& B, hipStream_t stream) {
-    hipError_t e = hipMemsetAsync(B.flags, 0, sizeof(uint32_t) * 4, stream);
+hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, float* row_min,
+                           double* lower_bound, uint32_t* flags, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, stream, flags);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(validate_kernel, dim3(n), dim3(256), 0, stream, mat_dense, n,
-                       is_distance ? 1 : 0, is_distance ? 1 : 0,
-                       want_row_min ? B.row_min : nullptr, B.flags);
+                       is_distance ? 1 : 0, is_distance ? 1 : 0, row_min, flags);
     e = hipGetLastError();
-    if (e != hipSuccess || !want_row_min) return e;
-    hipLaunchKernelGGL(lower_bound_kernel, dim3(1), dim3(1), 0, stream, B.row_min, n,
-                       B.lower_bound);
+    if (e != hipSuccess || !lower_bound) return e;
+    hipLaunchKernelGGL(lower_bound_kernel, dim3(1), dim3(1), 0, stream, row_min, n, lower_bound);
     return hipGetLastError();
 }
 
@@ -335,6 +490,36 @@ hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32
                        apply_deposit ? 1 : 0, 1.0 - static_cast<double>(rho), ldexp(1.0, -S),
                        static_cast<double>(alpha), static_cast<double>(beta),
                        static_cast<double>(gamma));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(const BatchDevice& BD, int32_t nrows, int32_t max_ld,
+                             const float* gamma_ptr, bool apply_deposit, float alpha, float beta,
+                             float rho, hipStream_t stream) {
+    const size_t lds = sizeof(double) * static_cast<size_t>(max_ld);
+    hipLaunchKernelGGL(batch_rows_kernel, dim3(nrows), dim3(64), lds, stream, BD.insts, BD.rows,
+                       nrows, BD.pools, gamma_ptr, apply_deposit ? 1 : 0,
+                       1.0 - static_cast<double>(rho), static_cast<double>(alpha),
+                       static_cast<double>(beta));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ants(const BatchDevice& BD, int32_t count, float Q, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_ants_kernel, dim3(count), dim3(256), 0, stream, BD.insts, BD.pools,
+                       BD.state, static_cast<double>(Q));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const BatchDevice& BD, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(1), 0, stream, BD.state, BD.gammas,
+                       BD.queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_arm(const BatchDevice& BD, uint32_t iter0, int32_t T,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(batch_arm_kernel, dim3(1), dim3(1), 0, stream, BD.state, BD.gammas,
+                       BD.queue, iter0, T);
     return hipGetLastError();
 }
 

@@ -1,0 +1,128 @@
+"""Construct schedules and the batched engine, through the C ABI.
+
+Every construct schedule (lanes per ant, live-block list) must give the same
+tours bit for bit, and every member of a batch must evolve exactly as the same
+instance run alone -- which the single-instance parity tests tie to the oracle.
+"""
+import numpy as np
+import pytest
+
+import aco_instances as inst
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("n", [3, 5, 31, 64, 65, 128, 129, 300, 1030])
+def test_every_schedule_builds_the_same_tours(n):
+    torch = _torch()
+    from paper_2404_04895_amd import SCHEDULES, Colony
+    D = inst.distance_matrix(inst.uniform_cities(n, 40 + n))
+    m = 37
+    ref = None
+    col = Colony(torch.from_numpy(D).cuda(), 1.0, 2.0, 0.3, 1.0, m)
+    col.transition(1.5)
+    P = col.P().cpu().numpy()
+    for sched in SCHEDULES:
+        col.set_schedule(sched)
+        col.construct(m, 9 + n, 3)
+        col.sync()
+        got = (col.tours(m).cpu().numpy().copy(), col.lengths(m).cpu().numpy().copy())
+        if ref is None:
+            ref = got
+            o_tours, o_len = oracle.construct(P, D, 9 + n, 3, np.arange(m))
+            assert np.array_equal(got[0], o_tours) and np.array_equal(got[1], o_len)
+        else:
+            assert np.array_equal(got[0], ref[0]), "schedule %d" % sched
+            assert np.array_equal(got[1], ref[1]), "schedule %d" % sched
+    col.close()
+
+
+def _batch_instances():
+    ns = [3, 4, 7, 16, 50, 63, 64, 65, 100, 128, 129, 250, 257, 400]
+    ms = [n if k % 3 else max(1, n // 2 + 3) for k, n in enumerate(ns)]
+    seeds = [1000 + 7 * k for k in range(len(ns))]
+    dists = [inst.distance_matrix(inst.uniform_cities(n, 500 + k)) for k, n in enumerate(ns)]
+    return ns, ms, seeds, dists
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_independent_runs(use_graph):
+    torch = _torch()
+    from paper_2404_04895_amd import Batch, Colony
+    ns, ms, seeds, dists = _batch_instances()
+    T, alpha, beta, rho, elite_k = 9, 1.0, 2.0, 0.2, 5
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = Batch(dists, alpha, beta, rho, 1.0, ants=ms, seeds=seeds, elite_k=elite_k,
+                  stream=stream)
+        b.run(T, use_graph=use_graph)
+        lens, its, tours = b.best()
+        for i, n in enumerate(ns):
+            col = Colony(torch.from_numpy(dists[i]).cuda(), alpha, beta, rho, 1.0, ms[i],
+                         elite_k=min(elite_k, ms[i]), stream=stream)
+            tour, L = col.run(ms[i], seeds[i], T)
+            _, _, it = col.best()
+            assert L == lens[i] and it == its[i], (i, n)
+            assert np.array_equal(tour, tours[i]), (i, n)
+            assert np.array_equal(col.tau().cpu().numpy(), b.tau(i).cpu().numpy()), (i, n)
+            assert np.array_equal(col.P().cpu().numpy(), b.P(i).cpu().numpy()), (i, n)
+            assert sorted(tours[i]) == list(range(n))
+            assert oracle.tour_length(tours[i], dists[i]) == lens[i]
+            col.close()
+        b.close()
+    stream.synchronize()
+
+
+def test_batch_schedule_tables_do_not_change_results():
+    torch = _torch()
+    from paper_2404_04895_amd import Batch, SCHED_G16, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE
+    ns, ms, seeds, dists = _batch_instances()
+    stream = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(stream):
+        for table, waves in [([], 0), ([(64, SCHED_G64), (10**6, SCHED_G64_LIVE)], 97),
+                             ([(400, SCHED_G32_LIVE)], 1), ([(10**6, SCHED_G16)], 4096)]:
+            b = Batch(dists, 1.0, 3.0, 0.1, 1.0, ants=ms, seeds=seeds, stream=stream)
+            b.set_schedules(table, waves)
+            b.run(5, use_graph=True)
+            lens, its, tours = b.best()
+            taus = [b.tau(i).cpu().numpy().copy() for i in range(len(ns))]
+            outs.append((lens, its, tours, taus))
+            b.close()
+    for lens, its, tours, taus in outs[1:]:
+        assert np.array_equal(lens, outs[0][0]) and np.array_equal(its, outs[0][1])
+        for i in range(len(ns)):
+            assert np.array_equal(tours[i], outs[0][2][i])
+            assert np.array_equal(taus[i], outs[0][3][i])
+
+
+def test_batch_consecutive_runs_continue_the_counter():
+    """Two runs of 3 iterations continue the generator's iteration counter and
+    the pheromone state: they equal a single-instance colony driven the same way."""
+    torch = _torch()
+    from paper_2404_04895_amd import Batch, Colony
+    ns, ms, seeds, dists = _batch_instances()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = Batch(dists[:5], 1.0, 2.0, 0.3, 1.0, ants=ms[:5], seeds=seeds[:5], stream=stream)
+        b.run(3)
+        b.run(3)
+        lens, _, _ = b.best()
+        for i in range(5):
+            col = Colony(torch.from_numpy(dists[i]).cuda(), 1.0, 2.0, 0.3, 1.0, ms[i],
+                         stream=stream)
+            col.run(ms[i], seeds[i], 3)
+            _, L = col.run(ms[i], seeds[i], 3)
+            assert L == lens[i]
+            assert np.array_equal(col.tau().cpu().numpy(), b.tau(i).cpu().numpy())
+            col.close()
+        b.close()
+    stream.synchronize()
