@@ -111,3 +111,30 @@ def batch_sizes(count: int = 512, lo: int = 50, hi: int = 500, seed: int = 0) ->
     """City counts of a batch of uneven instances, uniform on [lo, hi]."""
     rng = np.random.default_rng(seed)
     return rng.integers(lo, hi + 1, size=count).astype(np.int32)
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchWorkload:
+    """Many independent uniform instances of uneven size (seed of instance i = i)."""
+    name: str
+    count: int
+    n_lo: int
+    n_hi: int
+    alpha: float
+    beta: float
+    rho: float
+    Q: float
+    iters: int
+    size_seed: int = 0
+
+    def sizes(self) -> np.ndarray:
+        return batch_sizes(self.count, self.n_lo, self.n_hi, self.size_seed)
+
+    def dists(self):
+        return [distance_matrix(uniform_cities(int(n), i)) for i, n in enumerate(self.sizes())]
+
+
+BATCH_WORKLOADS = {
+    "batched-512-uniform-n50-500": BatchWorkload("batched-512-uniform-n50-500", 512, 50, 500,
+                                                 1.0, 2.0, 0.2, 1.0, 300),
+}

@@ -93,6 +93,90 @@ def cpu_baseline(w, D, P, budget_s=15.0):
     }
 
 
+def cpu_baseline_batch(w, dists, budget_s=15.0):
+    """The oracle on whole iterations of a sample of the batch's instances."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    steps, spent, used = 0, 0.0, 0
+    for i, D in enumerate(dists):
+        n = D.shape[0]
+        t0 = time.perf_counter()
+        oracle.run(D, n, w.alpha, w.beta, w.rho, w.Q, i, 2)
+        spent += time.perf_counter() - t0
+        steps += 2 * n * (n - 1)
+        used += 1
+        if spent > budget_s:
+            break
+    return {
+        "value": steps / spent,
+        "unit": "ant-steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "2 whole iterations of each of the first %d of %d instances (%.1f s)" % (
+            used, len(dists), spent),
+    }
+
+
+def bench_batch(args, w):
+    import numpy as np
+    import torch
+
+    from paper_2404_04895_amd import Batch, autotune
+
+    dists = w.dists()
+    ns = np.array([d.shape[0] for d in dists], dtype=np.int64)
+    table, waves = autotune.load_table()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = Batch(dists, w.alpha, w.beta, w.rho, w.Q, stream=stream)
+        b.set_schedules(table, waves)
+        if args.warmup:
+            b.run(args.warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        b.run(args.steps, use_graph=True)
+        stream.synchronize()
+        elapsed = time.perf_counter() - t0
+        lens, _, _ = b.best()
+        b.run(args.steps, use_graph=False, time_construct=True)
+        construct_ms, launches = b.construct_time()
+        b.close()
+    stream.synchronize()
+    ant_steps = int((ns * (ns - 1)).sum())
+    bytes_launch = int((ns * (ns - 1) * (4 * ns + 8)).sum())
+    avg_construct_s = construct_ms / launches / 1e3
+    achieved = bytes_launch / avg_construct_s / 1e9
+    line = {
+        "metric": "ant-steps/sec & % HBM peak; learned-vs-plain best-tour gap at equal time",
+        "value": ant_steps * args.steps / elapsed,
+        "unit": "ant-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": w.count, "n": [w.n_lo, w.n_hi],
+                   "m": "n", "alpha": w.alpha, "beta": w.beta, "rho": w.rho, "Q": w.Q,
+                   "cities": "uniform", "schedule_table": table, "persistent_waves": waves,
+                   "graph": True},
+        "roofline": {"bound": "hbm", "kernel": "batch_construct_kernel", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bytes_launch,
+                     "avg_launch_ms": avg_construct_s * 1e3},
+        "construct_ant_steps_per_s": ant_steps / avg_construct_s,
+        "mean_best_len": float(np.mean(lens)),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batch(w, dists)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +200,9 @@ def main():
     import aco_instances as inst
     from paper_2404_04895_amd import Colony, gamma_schedule
 
+    if args.workload in inst.BATCH_WORKLOADS:
+        bench_batch(args, inst.BATCH_WORKLOADS[args.workload])
+        return
     w = inst.WORKLOADS[args.workload]
     n, m, T = w.n, w.m, w.iters
     D = w.dist(args.seed)

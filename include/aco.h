@@ -256,12 +256,24 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
 aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table,
                                    int32_t entries, int32_t persistent_waves);
 
+/* Flags of aco_batch_run. */
+#define ACO_BATCH_GRAPH 1          /* capture one iteration once, replay it      */
+#define ACO_BATCH_TIME_CONSTRUCT 2 /* launch directly and time every construct   */
+
 /* Run `iters` iterations on every instance, from its current pheromone state
  * and the batch's running iteration counter, with the cosine gamma schedule
  * over `iters` (as aco_run).  Clears the best-so-far records first.  Enqueues
- * and returns; use_graph != 0 (with a non-null stream) captures one iteration
- * once and replays it.  Errors: ACO_EINVAL for iters outside [0, 65535]. */
-aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t use_graph);
+ * and returns.  flags: ACO_BATCH_GRAPH (needs a non-null stream) captures one
+ * iteration once and replays it; ACO_BATCH_TIME_CONSTRUCT launches directly
+ * and records a HIP event pair around each persistent construct launch (read
+ * with aco_batch_construct_time).  Errors: ACO_EINVAL for iters outside
+ * [0, 65535]. */
+aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t flags);
+
+/* Total and count of the construct launches timed by the last run with
+ * ACO_BATCH_TIME_CONSTRUCT (milliseconds, HIP events on the batch's stream).
+ * Blocks. */
+aco_status aco_batch_construct_time(aco_batch* b, double* ms_total, int32_t* launches);
 
 /* Best-so-far length and iteration of every instance (host arrays of count
  * entries) and the best tours concatenated in instance order (sum of n_i

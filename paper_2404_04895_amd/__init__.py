@@ -280,8 +280,18 @@ class Batch:
         check(lib().aco_batch_set_schedules(self._b, arr, len(table), persistent_waves),
               "aco_batch_set_schedules")
 
-    def run(self, iters, use_graph=True):
-        check(lib().aco_batch_run(self._b, iters, 1 if use_graph else 0), "aco_batch_run")
+    def run(self, iters, use_graph=True, time_construct=False):
+        flags = (_native.BATCH_GRAPH if use_graph else 0) | (
+            _native.BATCH_TIME_CONSTRUCT if time_construct else 0)
+        check(lib().aco_batch_run(self._b, iters, flags), "aco_batch_run")
+
+    def construct_time(self):
+        """(total ms, launches) of the construct launches timed by the last run."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int32()
+        check(lib().aco_batch_construct_time(self._b, ctypes.byref(ms), ctypes.byref(k)),
+              "aco_batch_construct_time")
+        return float(ms.value), int(k.value)
 
     def sync(self):
         check(lib().aco_batch_sync(self._b), "aco_batch_sync")

@@ -34,6 +34,7 @@ class BatchView(ctypes.Structure):
 
 SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE = -1, 0, 1, 2, 3, 4
 SCHEDULES = (SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE)
+BATCH_GRAPH, BATCH_TIME_CONSTRUCT = 1, 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -72,6 +73,8 @@ SIGNATURES = {
     "aco_batch_run": (_i32, [_vp, _i32, _i32]),
     "aco_batch_best": (_i32, [_vp, _vp, _vp, _vp]),
     "aco_batch_instance": (_i32, [_vp, _i32, ctypes.POINTER(BatchView)]),
+    "aco_batch_construct_time": (_i32, [_vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_i32)]),
     "aco_batch_sync": (_i32, [_vp]),
     "aco_batch_destroy": (None, [_vp]),
     "aco_sync": (_i32, [_vp]),

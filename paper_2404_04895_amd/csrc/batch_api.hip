@@ -96,10 +96,13 @@ struct aco_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_stale = true;
+    std::vector<hipEvent_t> events;  // construct timing: a start/stop pair per iteration
+    int32_t timed_launches = 0;
 
     ~aco_batch() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
 };
 
@@ -136,9 +139,12 @@ aco_status upload_tasks(aco_batch* b) {
     return ACO_OK;
 }
 
-aco_status enqueue_iteration(aco_batch* b) {
+aco_status enqueue_iteration(aco_batch* b, hipEvent_t before = nullptr,
+                             hipEvent_t after = nullptr) {
+    if (before) ACO_HIP(hipEventRecord(before, b->stream), "event record");
     ACO_HIP(aco::launch_batch_construct(b->dev, b->ntasks, b->task_lds, b->waves, b->stream),
             "batch construct");
+    if (after) ACO_HIP(hipEventRecord(after, b->stream), "event record");
     ACO_HIP(aco::launch_batch_ants(b->dev, b->count, b->Q, b->stream), "batch ants");
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, &b->dev.state->gamma_next,
                                    true, b->alpha, b->beta, b->rho, b->stream),
@@ -345,7 +351,7 @@ aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table
     return upload_tasks(b);
 }
 
-aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t use_graph) {
+aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t flags) {
     if (!b) return fail(ACO_EINVAL, "null batch");
     if (iters < 0 || iters > kMaxRunIters)
         return fail(ACO_EINVAL, "aco_batch_run: iters outside [0, %d]", kMaxRunIters);
@@ -366,17 +372,28 @@ aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t use_graph) {
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, b->dev.gammas, false,
                                    b->alpha, b->beta, b->rho, b->stream),
             "batch transition");
-    const bool graph = use_graph && b->stream != nullptr;
+    const bool timed = (flags & ACO_BATCH_TIME_CONSTRUCT) != 0;
+    const bool graph = !timed && (flags & ACO_BATCH_GRAPH) && b->stream != nullptr;
     if (graph && (b->graph_stale || !b->graph_exec)) {
         if (aco_status st = build_graph(b)) return st;
+    }
+    b->timed_launches = 0;
+    if (timed) {
+        while (b->events.size() < 2 * static_cast<size_t>(iters)) {
+            hipEvent_t ev = nullptr;
+            ACO_HIP(hipEventCreate(&ev), "event create");
+            b->events.push_back(ev);
+        }
     }
     for (int32_t it = 0; it < iters; ++it) {
         if (graph) {
             ACO_HIP(hipGraphLaunch(b->graph_exec, b->stream), "graph launch");
-        } else if (aco_status st = enqueue_iteration(b)) {
+        } else if (aco_status st = enqueue_iteration(b, timed ? b->events[2 * it] : nullptr,
+                                                     timed ? b->events[2 * it + 1] : nullptr)) {
             return st;
         }
     }
+    if (timed) b->timed_launches = iters;
     b->iter += static_cast<uint32_t>(iters);
     return ACO_OK;
 }
@@ -415,6 +432,20 @@ aco_status aco_batch_instance(const aco_batch* b, int32_t i, aco_batch_view* vie
     view->tours = b->dev.pools.tours + in.off_tours;
     view->lengths = b->dev.pools.lengths + in.off_ants;
     view->best_tour = b->dev.pools.best_tour + in.off_cities;
+    return ACO_OK;
+}
+
+aco_status aco_batch_construct_time(aco_batch* b, double* ms_total, int32_t* launches) {
+    if (!b) return fail(ACO_EINVAL, "null batch");
+    ACO_HIP(hipStreamSynchronize(b->stream), "construct time (sync)");
+    double total = 0.0;
+    for (int32_t it = 0; it < b->timed_launches; ++it) {
+        float ms = 0.0f;
+        ACO_HIP(hipEventElapsedTime(&ms, b->events[2 * it], b->events[2 * it + 1]), "elapsed");
+        total += ms;
+    }
+    if (ms_total) *ms_total = total;
+    if (launches) *launches = b->timed_launches;
     return ACO_OK;
 }
 
