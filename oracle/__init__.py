@@ -67,6 +67,19 @@ def lib():
                                             _i32p, _f32p, _i32p, _f32p]),
             "oracle_tsp_exact": (ctypes.c_double, [_f32p, ctypes.c_int32, _i32p]),
             "oracle_to_unit_many": (None, [_u32p, ctypes.c_int64, _f32p]),
+            "oracle_mlp_param_count": (ctypes.c_int32, []),
+            "oracle_bf16_round": (ctypes.c_float, [ctypes.c_float]),
+            "oracle_edge_ranks": (None, [_f32p, ctypes.c_int32, _i32p]),
+            "oracle_mean_nn": (ctypes.c_double, [_f32p, ctypes.c_int32]),
+            "oracle_edge_features": (None, [_f32p, _i32p, ctypes.c_int32, ctypes.c_double,
+                                            _f32p]),
+            "oracle_mlp_forward": (None, [_f64p, _f32p, ctypes.c_int64, ctypes.c_int32, _f64p,
+                                          _f64p]),
+            "oracle_mlp_loss_grad": (ctypes.c_double, [_f64p, _f32p, _f32p, ctypes.c_int64,
+                                                       ctypes.c_int32, _f64p]),
+            "oracle_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double]),
             "oracle_start_cities": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
                                            ctypes.c_int32, _i32p]),
             "oracle_select_many": (None, [_f32p, _f64p, _u8p, ctypes.c_int32, ctypes.c_double,
@@ -268,3 +281,70 @@ def select_many(row, visited, seed, t, s, count, *, gamma=1.0, literal=False):
         lib().oracle_select_many(_ptr(r, ctypes.c_float), None, _ptr(vis, ctypes.c_uint8), n,
                                  gamma, 0, seed, t, s, count, _ptr(out, ctypes.c_int32))
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned edge heuristic (mlp_oracle.c)
+# ---------------------------------------------------------------------------
+def mlp_param_count():
+    return lib().oracle_mlp_param_count()
+
+
+def bf16_round(x):
+    return lib().oracle_bf16_round(float(x))
+
+
+def edge_ranks(dist):
+    dist = _c(dist, np.float32)
+    n = dist.shape[0]
+    rank = np.zeros((n, n), np.int32)
+    lib().oracle_edge_ranks(_ptr(dist, ctypes.c_float), n, _ptr(rank, ctypes.c_int32))
+    return rank
+
+
+def mean_nn(dist):
+    dist = _c(dist, np.float32)
+    return lib().oracle_mean_nn(_ptr(dist, ctypes.c_float), dist.shape[0])
+
+
+def edge_features(dist, rank=None, mean=None):
+    """(n, n, 3) float32 features; the diagonal is zero."""
+    dist = _c(dist, np.float32)
+    n = dist.shape[0]
+    rank = edge_ranks(dist) if rank is None else _c(rank, np.int32)
+    mean = mean_nn(dist) if mean is None else float(mean)
+    feats = np.zeros((n, n, 3), np.float32)
+    lib().oracle_edge_features(_ptr(dist, ctypes.c_float), _ptr(rank, ctypes.c_int32), n, mean,
+                               _ptr(feats, ctypes.c_float))
+    return feats
+
+
+def mlp_forward(params, feats, round_bf16=True):
+    """(z, eta) for (count, 3) features."""
+    params = _c(params, np.float64)
+    feats = _c(feats, np.float32).reshape(-1, 3)
+    z = np.zeros(feats.shape[0], np.float64)
+    eta = np.zeros(feats.shape[0], np.float64)
+    lib().oracle_mlp_forward(_ptr(params, ctypes.c_double), _ptr(feats, ctypes.c_float),
+                             feats.shape[0], 1 if round_bf16 else 0, _ptr(z, ctypes.c_double),
+                             _ptr(eta, ctypes.c_double))
+    return z, eta
+
+
+def mlp_loss_grad(params, feats, y, round_bf16=True):
+    params = _c(params, np.float64)
+    feats = _c(feats, np.float32).reshape(-1, 3)
+    y = _c(y, np.float32)
+    grad = np.zeros(mlp_param_count(), np.float64)
+    loss = lib().oracle_mlp_loss_grad(_ptr(params, ctypes.c_double), _ptr(feats, ctypes.c_float),
+                                      _ptr(y, ctypes.c_float), feats.shape[0],
+                                      1 if round_bf16 else 0, _ptr(grad, ctypes.c_double))
+    return loss, grad
+
+
+def adam_step(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on float64 arrays params, m, v."""
+    g = _c(grad, np.float64)
+    lib().oracle_adam_step(_ptr(params, ctypes.c_double), _ptr(m, ctypes.c_double),
+                           _ptr(v, ctypes.c_double), _ptr(g, ctypes.c_double), params.shape[0],
+                           t, lr, b1, b2, eps)

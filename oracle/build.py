@@ -9,7 +9,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "aco_oracle.c")
+SRCS = [os.path.join(HERE, "aco_oracle.c"), os.path.join(HERE, "mlp_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
@@ -17,7 +17,7 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-        "-o", LIB + ".tmp", SRC, "-lm",
+        "-o", LIB + ".tmp", *SRCS, "-lm",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)
