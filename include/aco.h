@@ -290,6 +290,95 @@ aco_status aco_batch_sync(aco_batch* b);
 /* Free the host object (the workspace stays the caller's). NULL is a no-op. */
 void aco_batch_destroy(aco_batch* b);
 
+/* ------------------------------------------------------------------------ */
+/* Learned heuristic: an edge MLP whose output replaces eta = 1/d in Eq. (1) */
+/* (Sec. 2.1) through aco_set_eta.  Not part of the paper.                   */
+/*   features  f1 = d_ij / dNN (dNN = mean nearest-neighbour distance),      */
+/*             f2 = log2(1 + rank_i(j)), f3 = log2(1 + rank_j(i)), where      */
+/*             rank_i(j) is j's 1-based position among i's neighbours by     */
+/*             distance, ties to the smaller index; each FP64, rounded once  */
+/*             to FP32                                                       */
+/*   network   3 -> 64 -> 64 -> 1, ReLU; parameters and the first hidden     */
+/*             layer in BF16, FP32 accumulation (MFMA for the 64 x 64 layer); */
+/*             eta = 1e-4 + (1 - 1e-4) sigmoid(z)                             */
+/*   params    ACO_MLP_PARAMS FP32 values in this order: W1[64][3], b1[64],  */
+/*             W2[64][64] (row = output unit), b2[64], W3[64], b3; a "BF16   */
+/*             parameter" array holds their BF16 roundings as FP32 values    */
+/*   training  mean BCE-with-logits against targets y in [0, 1]; gradient    */
+/*             passes the rounding points through as the identity; Adam      */
+/*             (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master parameters, */
+/*             re-rounded to BF16 after each step.                            */
+/* All pointers are device pointers unless named _host; every call enqueues  */
+/* on hip_stream.                                                            */
+/* ------------------------------------------------------------------------ */
+#define ACO_MLP_PARAMS 4481
+
+/* kNN ranks of every city pair (rank_dev: n x n int32, rank_i(i) = 0), each
+ * city's nearest-neighbour distance (nn_dist_dev: n FP32) and their mean
+ * (mean_nn_dev: one FP64, summed in city order).  dist as aco_create's. */
+aco_status aco_edge_ranks(const float* dist_dev, int32_t n, int32_t* rank_dev, float* nn_dist_dev,
+                          double* mean_nn_dev, void* hip_stream);
+
+/* eta for every edge (eta_dev: n x n dense FP32; diagonal 0) from BF16
+ * parameters; adds the number of non-finite outputs to *nonfinite_dev (the
+ * caller zeroes it first; aco_set_eta also falls back to 1/d on them). */
+aco_status aco_mlp_eta(const float* bf16_params_dev, const float* dist_dev,
+                       const int32_t* rank_dev, const double* mean_nn_dev, int32_t n,
+                       float* eta_dev, uint32_t* nonfinite_dev, void* hip_stream);
+
+/* Features of the n (n - 1) off-diagonal edges, row by row with the diagonal
+ * skipped (feats_dev: n (n - 1) x 3 FP32). */
+aco_status aco_mlp_features(const float* dist_dev, const int32_t* rank_dev,
+                            const double* mean_nn_dev, int32_t n, float* feats_dev,
+                            void* hip_stream);
+
+/* Training targets y_ij = tau_ij / max_{k != i} tau_ik in the same edge order
+ * (tau_dev: n x ld FP32, e.g. aco_pheromone; y_dev: n (n - 1) FP32). */
+aco_status aco_mlp_targets(const float* tau_dev, int32_t n, int32_t ld, float* y_dev,
+                           void* hip_stream);
+
+/* BF16 rounding (nearest, ties to even) of ACO_MLP_PARAMS values. */
+aco_status aco_mlp_round(const float* params_dev, float* bf16_params_dev, void* hip_stream);
+
+typedef struct aco_mlp_trainer aco_mlp_trainer;
+
+/* Device workspace for a trainer with minibatches of `batch` edges (0 if
+ * batch < 1). */
+size_t aco_mlp_trainer_workspace_bytes(int32_t batch);
+
+/* Create a trainer from ACO_MLP_PARAMS FP32 initial parameters (copied).
+ * The caller's workspace (256-byte aligned) must stay valid until destroy. */
+aco_status aco_mlp_trainer_create(const float* init_params_dev, int32_t batch,
+                                  void* workspace_dev, size_t workspace_bytes, void* hip_stream,
+                                  aco_mlp_trainer** out);
+
+/* Gradient of the mean loss over `count` given edges (1 <= count <= batch;
+ * feats count x 3, y count) at the current BF16 parameters, into grad_dev
+ * (ACO_MLP_PARAMS FP32; may be NULL).  Updates nothing. */
+aco_status aco_mlp_trainer_gradient(aco_mlp_trainer* t, const float* feats_dev,
+                                    const float* y_dev, int32_t count, float* grad_dev);
+
+/* One Adam step with the last gradient (learning rate lr > 0).
+ * Errors: ACO_ESTATE before any gradient. */
+aco_status aco_mlp_trainer_apply(aco_mlp_trainer* t, float lr);
+
+/* One training step: a minibatch of `batch` edges drawn with replacement from
+ * the `count` edges of (feats_dev, y_dev) by the counter-based generator
+ * (key = seed, counter = (b / 4, step, 0xFFFFFFFE, 0)), its gradient, and one
+ * Adam step. */
+aco_status aco_mlp_trainer_step(aco_mlp_trainer* t, const float* feats_dev, const float* y_dev,
+                                int64_t count, uint64_t seed, float lr);
+
+/* Copy the FP32 master and/or the BF16 parameters out (either may be NULL). */
+aco_status aco_mlp_trainer_params(const aco_mlp_trainer* t, float* master_dev,
+                                  float* bf16_params_dev);
+
+/* Mean loss of the last gradient (blocks). */
+aco_status aco_mlp_trainer_loss(aco_mlp_trainer* t, double* loss_host);
+
+/* Free the host object.  NULL is a no-op. */
+void aco_mlp_trainer_destroy(aco_mlp_trainer* t);
+
 /* Diagnostic: write the deviates r_j, j = 0..count-1, that ant a draws at step
  * s of iteration t (see the header comment) to out_dev (device, count FP32),
  * on hip_stream.  Errors: ACO_EINVAL for count < 0. */

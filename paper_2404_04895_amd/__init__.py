@@ -16,10 +16,12 @@ from ._native import (SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G6
                       SCHED_G64_LIVE, SCHEDULES, AcoError, AcoParams, BatchView, ScheduleEntry,
                       check, lib)
 
-__all__ = ["Colony", "Batch", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
+__all__ = ["Colony", "Batch", "MlpTrainer", "edge_ranks", "mlp_eta", "mlp_features",
+           "mlp_targets", "mlp_round", "MLP_PARAMS", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
            "leading_dim", "MAX_CITIES", "SCHEDULES", "SCHED_AUTO"]
 
 MAX_CITIES = _native.MAX_CITIES
+MLP_PARAMS = _native.MLP_PARAMS
 
 
 def _torch():
@@ -334,3 +336,134 @@ class Batch:
     def lengths(self, i):
         v = self.view(i)
         return self._dev(v.lengths, _torch().float32, (v.m,))
+
+
+# ---------------------------------------------------------------------------
+# Learned edge heuristic
+# ---------------------------------------------------------------------------
+def _dev_f32(x, device="cuda"):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
+    return x.to(device=device, dtype=torch.float32).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def edge_ranks(dist, stream=None):
+    """(rank (n, n) int32, nearest-neighbour distance (n,), mean (1,) float64), on the device."""
+    torch = _torch()
+    d = _dev_f32(dist)
+    n = d.shape[0]
+    rank = torch.empty((n, n), dtype=torch.int32, device=d.device)
+    nn = torch.empty(n, dtype=torch.float32, device=d.device)
+    mean = torch.empty(1, dtype=torch.float64, device=d.device)
+    check(lib().aco_edge_ranks(_ptr(d), n, _ptr(rank), _ptr(nn), _ptr(mean),
+                               _stream_handle(stream)), "aco_edge_ranks")
+    return rank, nn, mean
+
+
+def mlp_eta(bf16_params, dist, rank=None, mean=None, stream=None):
+    """(eta (n, n) float32, number of non-finite outputs)."""
+    torch = _torch()
+    d = _dev_f32(dist)
+    n = d.shape[0]
+    if rank is None or mean is None:
+        rank, _, mean = edge_ranks(d, stream)
+    params = _dev_f32(bf16_params, d.device)
+    eta = torch.empty((n, n), dtype=torch.float32, device=d.device)
+    bad = torch.zeros(1, dtype=torch.int32, device=d.device)
+    check(lib().aco_mlp_eta(_ptr(params), _ptr(d), _ptr(rank), _ptr(mean), n, _ptr(eta),
+                            _ptr(bad), _stream_handle(stream)), "aco_mlp_eta")
+    return eta, bad
+
+
+def mlp_features(dist, rank=None, mean=None, stream=None):
+    torch = _torch()
+    d = _dev_f32(dist)
+    n = d.shape[0]
+    if rank is None or mean is None:
+        rank, _, mean = edge_ranks(d, stream)
+    feats = torch.empty((n * (n - 1), 3), dtype=torch.float32, device=d.device)
+    check(lib().aco_mlp_features(_ptr(d), _ptr(rank), _ptr(mean), n, _ptr(feats),
+                                 _stream_handle(stream)), "aco_mlp_features")
+    return feats
+
+
+def mlp_targets(tau_padded, n, stream=None):
+    torch = _torch()
+    tau = tau_padded.contiguous()
+    y = torch.empty(n * (n - 1), dtype=torch.float32, device=tau.device)
+    check(lib().aco_mlp_targets(_ptr(tau), n, tau.shape[1], _ptr(y), _stream_handle(stream)),
+          "aco_mlp_targets")
+    return y
+
+
+def mlp_round(params, stream=None):
+    torch = _torch()
+    p = _dev_f32(params)
+    out = torch.empty_like(p)
+    check(lib().aco_mlp_round(_ptr(p), _ptr(out), _stream_handle(stream)), "aco_mlp_round")
+    return out
+
+
+class MlpTrainer:
+    """Minibatch Adam training of the edge MLP on the device."""
+
+    def __init__(self, init_params, batch, device="cuda", stream=None):
+        torch = _torch()
+        p = _dev_f32(init_params, device)
+        assert p.numel() == MLP_PARAMS
+        self.batch = int(batch)
+        self._stream = stream
+        nbytes = lib().aco_mlp_trainer_workspace_bytes(self.batch)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=p.device)
+        h = ctypes.c_void_p()
+        self._t = None
+        check(lib().aco_mlp_trainer_create(_ptr(p), self.batch, _ptr(self.workspace), nbytes,
+                                           _stream_handle(stream), ctypes.byref(h)),
+              "aco_mlp_trainer_create")
+        self._t = h
+        self.device = p.device
+
+    def close(self):
+        if self._t is not None:
+            lib().aco_mlp_trainer_destroy(self._t)
+            self._t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gradient(self, feats, y):
+        torch = _torch()
+        f = _dev_f32(feats, self.device).reshape(-1, 3).contiguous()
+        yy = _dev_f32(y, self.device)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        check(lib().aco_mlp_trainer_gradient(self._t, _ptr(f), _ptr(yy), f.shape[0], _ptr(g)),
+              "aco_mlp_trainer_gradient")
+        return g
+
+    def apply(self, lr):
+        check(lib().aco_mlp_trainer_apply(self._t, lr), "aco_mlp_trainer_apply")
+
+    def step(self, feats, y, seed, lr):
+        check(lib().aco_mlp_trainer_step(self._t, _ptr(feats), _ptr(y), y.numel(), seed, lr),
+              "aco_mlp_trainer_step")
+
+    def loss(self):
+        v = ctypes.c_double()
+        check(lib().aco_mlp_trainer_loss(self._t, ctypes.byref(v)), "aco_mlp_trainer_loss")
+        return float(v.value)
+
+    def params(self):
+        torch = _torch()
+        master = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        eff = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        check(lib().aco_mlp_trainer_params(self._t, _ptr(master), _ptr(eff)),
+              "aco_mlp_trainer_params")
+        return master, eff

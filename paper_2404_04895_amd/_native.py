@@ -14,6 +14,7 @@ ACO_OK, ACO_EINVAL, ACO_ENOMEM, ACO_EDEVICE, ACO_ESTATE = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "ACO_OK", -1: "ACO_EINVAL", -2: "ACO_ENOMEM", -3: "ACO_EDEVICE",
                 -4: "ACO_ESTATE"}
 MAX_CITIES = 16384
+MLP_PARAMS = 4481
 
 
 class AcoParams(ctypes.Structure):
@@ -77,6 +78,20 @@ SIGNATURES = {
                                         ctypes.POINTER(_i32)]),
     "aco_batch_sync": (_i32, [_vp]),
     "aco_batch_destroy": (None, [_vp]),
+    "aco_edge_ranks": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "aco_mlp_eta": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "aco_mlp_features": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "aco_mlp_targets": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "aco_mlp_round": (_i32, [_vp, _vp, _vp]),
+    "aco_mlp_trainer_workspace_bytes": (ctypes.c_size_t, [_i32]),
+    "aco_mlp_trainer_create": (_i32, [_vp, _i32, _vp, ctypes.c_size_t, _vp,
+                                      ctypes.POINTER(_vp)]),
+    "aco_mlp_trainer_gradient": (_i32, [_vp, _vp, _vp, _i32, _vp]),
+    "aco_mlp_trainer_apply": (_i32, [_vp, _f32]),
+    "aco_mlp_trainer_step": (_i32, [_vp, _vp, _vp, ctypes.c_int64, _u64, _f32]),
+    "aco_mlp_trainer_params": (_i32, [_vp, _vp, _vp]),
+    "aco_mlp_trainer_loss": (_i32, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "aco_mlp_trainer_destroy": (None, [_vp]),
     "aco_sync": (_i32, [_vp]),
     "aco_destroy": (None, [_vp]),
     "aco_last_error": (ctypes.c_char_p, []),

@@ -1,0 +1,161 @@
+"""Learned edge heuristic on the GPU against the FP64 oracle, through the C ABI.
+
+Bars: ranks bit-exact; mean nearest-neighbour distance bit-exact (same FP64
+sum order); features within one FP32 ulp; z within 1e-4 (1 + |z|) (64-term
+FP32 accumulations on MFMA against FP64, on BF16 operands that are identical on
+both sides); gradients within relative L2 1e-3 of the oracle's FP64 gradient
+at the same BF16 parameters; one Adam step within 1e-6 relative of the
+oracle's FP64 step from the same gradient.
+"""
+import numpy as np
+import pytest
+
+import aco_instances as inst
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+OFF_W3 = 4416
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _init_params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(4481, np.float32)
+    p[0:192] = rng.standard_normal(192) * np.sqrt(2.0 / 3.0) * scale
+    p[192:256] = rng.standard_normal(64) * 0.1
+    p[256:4352] = rng.standard_normal(4096) * np.sqrt(2.0 / 64.0) * scale
+    p[4352:4416] = rng.standard_normal(64) * 0.1
+    p[4416:4480] = rng.standard_normal(64) * np.sqrt(1.0 / 64.0) * scale
+    p[4480] = -1.0
+    return p
+
+
+@pytest.mark.parametrize("n", [3, 4, 37, 300, 1100])
+def test_ranks_and_features_match_oracle(n):
+    torch = _torch()
+    from paper_2404_04895_amd import edge_ranks, mlp_features
+    D = inst.distance_matrix(inst.clustered_cities(n, 70 + n, 5, 0.03))
+    if n == 4:
+        D = inst.distance_matrix(np.array([[0, 0], [1, 0], [1, 1], [0, 1]], np.float32))
+    rank, nn, mean = edge_ranks(D)
+    R = rank.cpu().numpy()
+    assert np.array_equal(R, oracle.edge_ranks(D))
+    assert mean.cpu().numpy()[0] == oracle.mean_nn(D)
+    F = mlp_features(D, rank, mean).cpu().numpy()
+    Fo = oracle.edge_features(D, R, oracle.mean_nn(D))
+    off = ~np.eye(n, dtype=bool)
+    Fo = Fo[off].reshape(-1, 3)
+    ulp = np.spacing(np.abs(Fo).astype(np.float32))
+    assert np.all(np.abs(F - Fo) <= ulp)
+
+
+def test_eta_matches_oracle():
+    torch = _torch()
+    from paper_2404_04895_amd import mlp_eta, mlp_round
+    n = 150
+    D = inst.distance_matrix(inst.clustered_cities(n, 3, 6, 0.04))
+    for seed in (0, 1):
+        p = _init_params(seed)
+        pb = mlp_round(p).cpu().numpy()
+        assert np.array_equal(pb, np.array([oracle.bf16_round(v) for v in p], np.float32))
+        eta, bad = mlp_eta(pb, D)
+        assert int(bad.item()) == 0
+        eta = eta.cpu().numpy().astype(np.float64)
+        F = oracle.edge_features(D).reshape(-1, 3)
+        z_o, eta_o = oracle.mlp_forward(pb.astype(np.float64), F, round_bf16=True)
+        z_o = z_o.reshape(n, n)
+        eta_o = eta_o.reshape(n, n)
+        off = ~np.eye(n, dtype=bool)
+        assert np.all(np.diag(eta) == 0)
+        # eta' = sigmoid' <= 1/4 of the bound on z
+        tol = 0.25 * 1e-4 * (1 + np.abs(z_o[off])) + 1e-7
+        assert np.all(np.abs(eta[off] - eta_o[off]) <= tol)
+        assert eta_o[off].std() > 1e-3  # the network is not trivially constant
+
+
+def test_gradient_and_adam_match_oracle():
+    torch = _torch()
+    from paper_2404_04895_amd import MlpTrainer
+    n = 60
+    D = inst.distance_matrix(inst.clustered_cities(n, 5, 4, 0.05))
+    F = oracle.edge_features(D)
+    off = ~np.eye(n, dtype=bool)
+    feats = F[off].reshape(-1, 3)[:1500]
+    rng = np.random.default_rng(9)
+    y = rng.random(feats.shape[0]).astype(np.float32)
+    p = _init_params(4)
+    t = MlpTrainer(p, batch=2048)
+    g = t.gradient(feats, y).cpu().numpy().astype(np.float64)
+    pb = np.array([oracle.bf16_round(v) for v in p], np.float64)
+    loss_o, g_o = oracle.mlp_loss_grad(pb, feats, y, round_bf16=True)
+    rel = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
+    assert rel <= 1e-3, rel
+    assert abs(t.loss() - loss_o) <= 1e-5 * abs(loss_o)
+    # one Adam step from the GPU's gradient
+    t.apply(1e-3)
+    master, eff = t.params()
+    master = master.cpu().numpy().astype(np.float64)
+    ref = p.astype(np.float64).copy()
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    oracle.adam_step(ref, m, v, g, 1, lr=1e-3)
+    assert np.allclose(master, ref, rtol=1e-6, atol=1e-9)
+    assert np.array_equal(eff.cpu().numpy(),
+                          np.array([oracle.bf16_round(x) for x in master.astype(np.float32)],
+                                   np.float32))
+    t.close()
+
+
+def test_training_reduces_loss():
+    torch = _torch()
+    from paper_2404_04895_amd import MlpTrainer
+    n = 200
+    D = inst.distance_matrix(inst.clustered_cities(n, 8, 6, 0.03))
+    F = oracle.edge_features(D)
+    off = ~np.eye(n, dtype=bool)
+    feats = F[off].reshape(-1, 3)
+    # a learnable target: near neighbours (low rank) are likely
+    y = (1.0 / (1.0 + np.exp(3.0 * (feats[:, 1] - 2.5)))).astype(np.float32)
+    tf = torch.from_numpy(feats).cuda()
+    ty = torch.from_numpy(y).cuda()
+    t = MlpTrainer(_init_params(1), batch=4096)
+    t.gradient(feats[:4096], y[:4096])
+    first = t.loss()
+    for step in range(300):
+        t.step(tf, ty, 11, 3e-3)
+    t.gradient(feats[:4096], y[:4096])
+    last = t.loss()
+    assert last < 0.8 * first, (first, last)
+    t.close()
+
+
+def test_learned_eta_drives_a_colony_and_nan_falls_back():
+    torch = _torch()
+    from paper_2404_04895_amd import Colony, mlp_eta, mlp_round
+    n, m = 80, 40
+    D = inst.distance_matrix(inst.clustered_cities(n, 2, 4, 0.05))
+    pb = mlp_round(_init_params(2)).cpu().numpy()
+    eta, bad = mlp_eta(pb, D)
+    col = Colony(torch.from_numpy(D).cuda(), 1.0, 2.0, 0.1, 1.0, m)
+    assert col.set_eta(eta) is True
+    col.transition(1.5)
+    col.construct(m, 1, 0)
+    col.sync()
+    P = col.P().cpu().numpy()
+    ref = oracle.transition(col.tau().cpu().numpy(), D, 1.0, 2.0, 1.5, eta=eta.cpu().numpy())
+    assert np.allclose(P, ref, rtol=1e-5, atol=1e-38)
+    o_tours, _ = oracle.construct(P, D, 1, 0, np.arange(m))
+    assert np.array_equal(col.tours(m).cpu().numpy(), o_tours)
+    bad_params = pb.copy()
+    bad_params[OFF_W3] = np.nan
+    eta_bad, nbad = mlp_eta(bad_params, D)
+    assert int(nbad.item()) > 0
+    assert col.set_eta(eta_bad) is False   # falls back to 1/d
+    col.close()
