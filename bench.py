@@ -177,6 +177,44 @@ def bench_batch(args, w):
     print(json.dumps(line), flush=True)
 
 
+def bench_learned(args):
+    """Learned eta against eta = 1/d at equal wall time on held-out clustered
+    n = 2000 instances (30 Gaussians, sigma 0.015), m = n, 300 iterations."""
+    import numpy as np
+
+    from paper_2404_04895_amd import learned
+
+    master = learned.load_weights()
+    if master is None:
+        raise SystemExit("no trained weights")
+    kappa, lam = learned.heuristic_config()
+    count = max(1, args.steps)
+    rows = learned.equal_time_comparison(learned.evaluation_instances(count), [0], master,
+                                         kappa=kappa, lam=lam, verbose=False)
+    gaps = np.array([r["gap"] for r in rows])
+    line = {
+        "metric": "ant-steps/sec & % HBM peak; learned-vs-plain best-tour gap at equal time",
+        "value": 100.0 * float(gaps.mean()),
+        "unit": "% shorter best tour (learned vs plain, equal wall time)",
+        "n_gpus": 1,
+        "steps": count,
+        "warmup": 0,
+        "ms_per_step": 1e3 * float(np.mean([r["plain_s"] for r in rows])),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "learned-clustered-n2000", "instances": count, "n": 2000,
+                   "m": 2000, "iters": 300, "alpha": 1.0, "beta": 2.0, "rho": 0.1,
+                   "cities": "clustered, 30 Gaussians sigma 0.015", "kappa": kappa,
+                   "lambda": lam},
+        "runs": [{k: r[k] for k in ("plain_len", "learned_len", "gap", "plain_s", "learned_s",
+                                    "learned_iters")} for r in rows],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +240,9 @@ def main():
 
     if args.workload in inst.BATCH_WORKLOADS:
         bench_batch(args, inst.BATCH_WORKLOADS[args.workload])
+        return
+    if args.workload == "learned-clustered-n2000":
+        bench_learned(args)
         return
     w = inst.WORKLOADS[args.workload]
     n, m, T = w.n, w.m, w.iters

@@ -299,8 +299,11 @@ void aco_batch_destroy(aco_batch* b);
 /*             distance, ties to the smaller index; each FP64, rounded once  */
 /*             to FP32                                                       */
 /*   network   3 -> 64 -> 64 -> 1, ReLU; parameters and the first hidden     */
-/*             layer in BF16, FP32 accumulation (MFMA for the 64 x 64 layer); */
-/*             eta = 1e-4 + (1 - 1e-4) sigmoid(z)                             */
+/*             layer in BF16, FP32 accumulation (MFMA for the 64 x 64 layer)  */
+/*   heuristic eta = sigmoid(z)^kappa / f1^lambda, in FP64: the network's     */
+/*             edge probability times a power of the plain 1/d (dNN is a     */
+/*             constant factor, which the row normalisation of Eq. (1)       */
+/*             removes)                                                      */
 /*   params    ACO_MLP_PARAMS FP32 values in this order: W1[64][3], b1[64],  */
 /*             W2[64][64] (row = output unit), b2[64], W3[64], b3; a "BF16   */
 /*             parameter" array holds their BF16 roundings as FP32 values    */
@@ -320,11 +323,13 @@ aco_status aco_edge_ranks(const float* dist_dev, int32_t n, int32_t* rank_dev, f
                           double* mean_nn_dev, void* hip_stream);
 
 /* eta for every edge (eta_dev: n x n dense FP32; diagonal 0) from BF16
- * parameters; adds the number of non-finite outputs to *nonfinite_dev (the
- * caller zeroes it first; aco_set_eta also falls back to 1/d on them). */
+ * parameters; kappa, lambda >= 0.  Adds the number of non-finite or zero
+ * outputs to *nonfinite_dev (the caller zeroes it first; aco_set_eta falls
+ * back to 1/d on them). */
 aco_status aco_mlp_eta(const float* bf16_params_dev, const float* dist_dev,
                        const int32_t* rank_dev, const double* mean_nn_dev, int32_t n,
-                       float* eta_dev, uint32_t* nonfinite_dev, void* hip_stream);
+                       float kappa, float lambda, float* eta_dev, uint32_t* nonfinite_dev,
+                       void* hip_stream);
 
 /* Features of the n (n - 1) off-diagonal edges, row by row with the diagonal
  * skipped (feats_dev: n (n - 1) x 3 FP32). */

@@ -73,8 +73,8 @@ def lib():
             "oracle_mean_nn": (ctypes.c_double, [_f32p, ctypes.c_int32]),
             "oracle_edge_features": (None, [_f32p, _i32p, ctypes.c_int32, ctypes.c_double,
                                             _f32p]),
-            "oracle_mlp_forward": (None, [_f64p, _f32p, ctypes.c_int64, ctypes.c_int32, _f64p,
-                                          _f64p]),
+            "oracle_mlp_forward": (None, [_f64p, _f32p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_double, ctypes.c_double, _f64p, _f64p]),
             "oracle_mlp_loss_grad": (ctypes.c_double, [_f64p, _f32p, _f32p, ctypes.c_int64,
                                                        ctypes.c_int32, _f64p]),
             "oracle_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, ctypes.c_int32,
@@ -319,15 +319,15 @@ def edge_features(dist, rank=None, mean=None):
     return feats
 
 
-def mlp_forward(params, feats, round_bf16=True):
-    """(z, eta) for (count, 3) features."""
+def mlp_forward(params, feats, round_bf16=True, kappa=1.0, lam=0.0):
+    """(z, eta) for (count, 3) features; eta = sigmoid(z)^kappa / f1^lam."""
     params = _c(params, np.float64)
     feats = _c(feats, np.float32).reshape(-1, 3)
     z = np.zeros(feats.shape[0], np.float64)
     eta = np.zeros(feats.shape[0], np.float64)
     lib().oracle_mlp_forward(_ptr(params, ctypes.c_double), _ptr(feats, ctypes.c_float),
-                             feats.shape[0], 1 if round_bf16 else 0, _ptr(z, ctypes.c_double),
-                             _ptr(eta, ctypes.c_double))
+                             feats.shape[0], 1 if round_bf16 else 0, kappa, lam,
+                             _ptr(z, ctypes.c_double), _ptr(eta, ctypes.c_double))
     return z, eta
 
 

@@ -18,8 +18,12 @@
  *              (W2[u][k]: unit u of layer 2 from unit k of layer 1), b2[64],
  *              W3[64], b3.
  *   forward    a1 = W1 f + b1, h1 = relu(a1), a2 = W2 r(h1) + b2,
- *              h2 = relu(a2), z = W3 h2 + b3,
- *              eta = 1e-4 + (1 - 1e-4) sigmoid(z).
+ *              h2 = relu(a2), z = W3 h2 + b3.
+ *   heuristic  eta = sigmoid(z)^kappa / f1^lambda: the network's edge
+ *              probability, raised to kappa, times the plain heuristic
+ *              1/d (up to the constant dNN, which cancels in the row
+ *              normalisation of Eq. (1)) raised to lambda; in FP64 through
+ *              log sigmoid(z) = -softplus(-z).
  *              With rounding on, every parameter is first rounded to BF16
  *              (round to nearest even) and r() rounds h1 to BF16; with it off
  *              r() is the identity and parameters are used as given.
@@ -149,15 +153,20 @@ static double edge_forward(const double* w, const float* f, int32_t round_bf16, 
 }
 
 ORACLE_API void oracle_mlp_forward(const double* params, const float* feats, int64_t count,
-                                   int32_t round_bf16, double* z_out, double* eta_out) {
+                                   int32_t round_bf16, double kappa, double lambda,
+                                   double* z_out, double* eta_out) {
     double w[NPARAM];
     effective_params(params, round_bf16, w);
 #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < count; ++e) {
         double a1[H], h1r[H], a2[H], h2[H];
-        double z = edge_forward(w, feats + 3 * e, round_bf16, a1, h1r, a2, h2);
+        const float* f = feats + 3 * e;
+        double z = edge_forward(w, f, round_bf16, a1, h1r, a2, h2);
         if (z_out) z_out[e] = z;
-        if (eta_out) eta_out[e] = 1e-4 + (1.0 - 1e-4) * sigmoid(z);
+        if (eta_out) {
+            double log_sig = -softplus(-z);
+            eta_out[e] = exp(kappa * log_sig - lambda * log((double)f[0]));
+        }
     }
 }
 

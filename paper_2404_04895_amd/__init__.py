@@ -365,8 +365,8 @@ def edge_ranks(dist, stream=None):
     return rank, nn, mean
 
 
-def mlp_eta(bf16_params, dist, rank=None, mean=None, stream=None):
-    """(eta (n, n) float32, number of non-finite outputs)."""
+def mlp_eta(bf16_params, dist, rank=None, mean=None, stream=None, kappa=1.0, lam=0.0):
+    """(eta (n, n) float32, number of non-finite outputs); eta = sigmoid(z)^kappa / f1^lam."""
     torch = _torch()
     d = _dev_f32(dist)
     n = d.shape[0]
@@ -375,8 +375,8 @@ def mlp_eta(bf16_params, dist, rank=None, mean=None, stream=None):
     params = _dev_f32(bf16_params, d.device)
     eta = torch.empty((n, n), dtype=torch.float32, device=d.device)
     bad = torch.zeros(1, dtype=torch.int32, device=d.device)
-    check(lib().aco_mlp_eta(_ptr(params), _ptr(d), _ptr(rank), _ptr(mean), n, _ptr(eta),
-                            _ptr(bad), _stream_handle(stream)), "aco_mlp_eta")
+    check(lib().aco_mlp_eta(_ptr(params), _ptr(d), _ptr(rank), _ptr(mean), n, kappa, lam,
+                            _ptr(eta), _ptr(bad), _stream_handle(stream)), "aco_mlp_eta")
     return eta, bad
 
 

@@ -79,7 +79,7 @@ SIGNATURES = {
     "aco_batch_sync": (_i32, [_vp]),
     "aco_batch_destroy": (None, [_vp]),
     "aco_edge_ranks": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
-    "aco_mlp_eta": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "aco_mlp_eta": (_i32, [_vp, _vp, _vp, _vp, _i32, _f32, _f32, _vp, _vp, _vp]),
     "aco_mlp_features": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "aco_mlp_targets": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "aco_mlp_round": (_i32, [_vp, _vp, _vp]),

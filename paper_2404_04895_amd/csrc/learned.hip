@@ -8,7 +8,10 @@
 //             the smaller index); each computed in FP64, rounded once to FP32
 //   network   a1 = W1 f + b1 (FP64, rounded to FP32), h1 = relu(a1) rounded to
 //             BF16; a2 = W2 h1 + b2 on MFMA (BF16 x BF16, FP32 accumulation);
-//             h2 = relu(a2); z = W3 h2 + b3 (FP32); eta = 1e-4 + (1-1e-4) sigmoid(z)
+//             h2 = relu(a2); z = W3 h2 + b3 (FP32)
+//   heuristic eta = sigmoid(z)^kappa / f1^lambda in FP64 (the network's edge
+//             probability times a power of the plain heuristic 1/d; the
+//             constant dNN cancels in the row normalisation of Eq. (1))
 //   params    4481 values: W1[64][3], b1[64], W2[64][64] (out x in), b2[64],
 //             W3[64], b3; the network uses their BF16 roundings
 //   training  mean BCE-with-logits against targets y, gradient with the
@@ -165,8 +168,10 @@ __device__ __forceinline__ void edge_features(const float* dist, const int32_t* 
     f2 = static_cast<float>(log2(1.0 + static_cast<double>(rank[static_cast<size_t>(j) * n + i])));
 }
 
-__device__ __forceinline__ float eta_of(float z) {
-    return static_cast<float>(1e-4 + (1.0 - 1e-4) / (1.0 + exp(-static_cast<double>(z))));
+__device__ __forceinline__ float eta_of(float z, float f1, double kappa, double lambda) {
+    const double nz = -static_cast<double>(z);
+    const double log_sig = -((nz > 0.0 ? nz : 0.0) + log1p(exp(-fabs(nz))));  // -softplus(-z)
+    return static_cast<float>(exp(kappa * log_sig - lambda * log(static_cast<double>(f1))));
 }
 
 // ---- ranks ---------------------------------------------------------------------
@@ -222,7 +227,8 @@ __global__ __launch_bounds__(256) void eta_kernel(const float* __restrict__ para
                                                   const float* __restrict__ dist,
                                                   const int32_t* __restrict__ rank,
                                                   const double* __restrict__ mean_nn_ptr,
-                                                  int32_t n, float* __restrict__ eta,
+                                                  int32_t n, double kappa, double lambda,
+                                                  float* __restrict__ eta,
                                                   uint32_t* __restrict__ nonfinite) {
     __shared__ float w[kMlpParams];
     for (int p = threadIdx.x; p < kMlpParams; p += 256) w[p] = params[p];
@@ -250,8 +256,9 @@ __global__ __launch_bounds__(256) void eta_kernel(const float* __restrict__ para
                 const int32_t io = static_cast<int32_t>(e_out / n), jo = static_cast<int32_t>(e_out % n);
                 float v = 0.0f;
                 if (io != jo) {
-                    v = eta_of(pick_z(t, col));
-                    if (!isfinite(v)) ++bad;
+                    const float f1o = static_cast<float>(static_cast<double>(dist[e_out]) / mean_nn);
+                    v = eta_of(pick_z(t, col), f1o, kappa, lambda);
+                    if (!isfinite(v) || !(v > 0.0f)) ++bad;
                 }
                 eta[e_out] = v;
             }
@@ -493,12 +500,12 @@ hipError_t launch_ranks(const float* dist, int32_t n, int32_t* rank, float* nn_d
 }
 
 hipError_t launch_eta(const float* params, const float* dist, const int32_t* rank,
-                      const double* mean_nn, int32_t n, float* eta, uint32_t* nonfinite,
-                      hipStream_t stream) {
+                      const double* mean_nn, int32_t n, double kappa, double lambda, float* eta,
+                      uint32_t* nonfinite, hipStream_t stream) {
     const int64_t tiles = (static_cast<int64_t>(n) * n + 31) / 32;
     const int64_t grid = std::min<int64_t>((tiles + 3) / 4, 8192);
     hipLaunchKernelGGL(eta_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, stream, params,
-                       dist, rank, mean_nn, n, eta, nonfinite);
+                       dist, rank, mean_nn, n, kappa, lambda, eta, nonfinite);
     return hipGetLastError();
 }
 

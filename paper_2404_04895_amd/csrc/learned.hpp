@@ -14,8 +14,8 @@ hipError_t prepare_learned_kernels();
 hipError_t launch_ranks(const float* dist, int32_t n, int32_t* rank, float* nn_dist,
                         double* mean_nn, hipStream_t stream);
 hipError_t launch_eta(const float* params, const float* dist, const int32_t* rank,
-                      const double* mean_nn, int32_t n, float* eta, uint32_t* nonfinite,
-                      hipStream_t stream);
+                      const double* mean_nn, int32_t n, double kappa, double lambda, float* eta,
+                      uint32_t* nonfinite, hipStream_t stream);
 hipError_t launch_features(const float* dist, const int32_t* rank, const double* mean_nn,
                            int32_t n, float* feats, hipStream_t stream);
 hipError_t launch_targets(const float* tau, int32_t n, int32_t ld, float* y, hipStream_t stream);

@@ -75,13 +75,16 @@ aco_status aco_edge_ranks(const float* dist_dev, int32_t n, int32_t* rank_dev, f
 }
 
 aco_status aco_mlp_eta(const float* params_dev, const float* dist_dev, const int32_t* rank_dev,
-                       const double* mean_nn_dev, int32_t n, float* eta_dev,
-                       uint32_t* nonfinite_dev, void* hip_stream) {
+                       const double* mean_nn_dev, int32_t n, float kappa, float lambda,
+                       float* eta_dev, uint32_t* nonfinite_dev, void* hip_stream) {
     if (!params_dev || !dist_dev || !rank_dev || !mean_nn_dev || !eta_dev || !nonfinite_dev)
         return fail(ACO_EINVAL, "aco_mlp_eta: NULL pointer");
     if (n < 3 || n > ACO_MAX_CITIES)
         return fail(ACO_EINVAL, "aco_mlp_eta: n = %d outside [3, %d]", n, ACO_MAX_CITIES);
-    ACO_HIP(aco::launch_eta(params_dev, dist_dev, rank_dev, mean_nn_dev, n, eta_dev,
+    if (!(isfinite(kappa) && kappa >= 0.0f && isfinite(lambda) && lambda >= 0.0f))
+        return fail(ACO_EINVAL, "aco_mlp_eta: kappa and lambda must be finite and >= 0");
+    ACO_HIP(aco::launch_eta(params_dev, dist_dev, rank_dev, mean_nn_dev, n,
+                            static_cast<double>(kappa), static_cast<double>(lambda), eta_dev,
                             nonfinite_dev, static_cast<hipStream_t>(hip_stream)),
             "eta");
     return ACO_OK;

@@ -1,0 +1,257 @@
+"""Training and evaluation of the learned edge heuristic.
+
+Training data: plain runs (eta = 1/d) of the method on clustered instances,
+run together on the batched engine; the converged pheromone of each instance
+gives the targets y_ij = tau_ij / max_k tau_ik of its edges, and the edge
+features come from the distances and kNN ranks.  The edge MLP is trained on
+the GPU (minibatch Adam) with the library's own forward, backward and Adam
+kernels.  Evaluation: the plain method against the same method with the
+learned eta, at equal wall time (the learned arm pays for ranks and inference
+out of its iteration budget), judged by the best tour length.
+
+    python -m paper_2404_04895_amd.learned train [--out FILE]
+    python -m paper_2404_04895_amd.learned evaluate [--weights FILE]
+"""
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "edge_mlp_clustered_n500.npy")
+
+
+def init_params(seed=0):
+    """He-style initial parameters (FP32, in the ABI's parameter order)."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(4481, np.float32)
+    p[0:192] = rng.standard_normal(192) * math.sqrt(2.0 / 3.0)
+    p[256:4352] = rng.standard_normal(4096) * math.sqrt(2.0 / 64.0)
+    p[4416:4480] = rng.standard_normal(64) * math.sqrt(1.0 / 64.0)
+    p[4480] = -3.0  # most edges are not in a converged tour
+    return p
+
+
+def training_set(count=200, n=500, clusters=20, sigma=0.02, seed0=1000, iters=300, alpha=1.0,
+                 beta=2.0, rho=0.1, runs=1, verbose=True):
+    """Features (N x 3) and targets (N) on the device from plain batched runs.
+    With runs > 1 each instance is run with `runs` generator seeds and its
+    targets are the mean of the runs' targets."""
+    import torch
+
+    import aco_instances as inst
+    from . import Batch, autotune, edge_ranks, mlp_features, mlp_targets
+
+    seeds = list(range(seed0, seed0 + count))
+    dists = [inst.distance_matrix(inst.clustered_cities(n, s, clusters, sigma)) for s in seeds]
+    table, waves = autotune.load_table()
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        b = Batch(dists * runs, alpha, beta, rho, 1.0, ants=[n] * (count * runs),
+                  seeds=[s + 100000 * r for r in range(runs) for s in seeds], stream=stream)
+        b.set_schedules(table, waves)
+        b.run(iters)
+        feats, ys = [], []
+        for i, D in enumerate(dists):
+            rank, _, mean = edge_ranks(D, stream)
+            feats.append(mlp_features(D, rank, mean, stream))
+            y = None
+            for r in range(runs):
+                v = b.view(i + r * count)
+                tau = b._dev(v.tau, torch.float32, (v.n, v.ld))
+                yr = mlp_targets(tau, n, stream)
+                y = yr if y is None else y + yr
+            ys.append(y / runs)
+        feats = torch.cat(feats)
+        y = torch.cat(ys)
+        b.close()
+    stream.synchronize()
+    if verbose:
+        print("training set: %d instances x %d edges in %.1f s (plain runs of %d iterations)" % (
+            count, n * (n - 1), time.perf_counter() - t0, iters), flush=True)
+    return feats, y
+
+
+def train(feats, y, steps=4000, batch=16384, lr=1e-3, seed=0, init_seed=0, verbose=True):
+    import torch
+
+    from . import MlpTrainer
+    t = MlpTrainer(init_params(init_seed), batch)
+    curve = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        t.step(feats, y, seed, lr)
+        if verbose and (k % 500 == 0 or k == steps - 1):
+            curve.append((k, t.loss()))
+            print("step %d: minibatch loss %.5f" % curve[-1], flush=True)
+    torch.cuda.synchronize()
+    master, eff = t.params()
+    elapsed = time.perf_counter() - t0
+    t.close()
+    return master.cpu().numpy(), eff.cpu().numpy(), curve, elapsed
+
+
+def save_weights(master, path=DEFAULT_WEIGHTS):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.save(path, np.asarray(master, np.float32), allow_pickle=False)
+
+
+def load_weights(path=DEFAULT_WEIGHTS):
+    """FP32 master parameters (ACO_MLP_PARAMS,), or None if there are none."""
+    if not os.path.exists(path):
+        return None
+    p = np.load(path, allow_pickle=False)
+    return p.astype(np.float32) if p.shape == (4481,) else None
+
+
+DEFAULT_KAPPA, DEFAULT_LAMBDA = 0.5, 1.0
+
+
+def heuristic_config(path=DEFAULT_WEIGHTS):
+    """(kappa, lambda) stored beside the weights by the validation sweep."""
+    cfg = path.replace(".npy", ".json")
+    try:
+        with open(cfg) as f:
+            c = json.load(f)
+        return float(c["kappa"]), float(c["lambda"])
+    except (OSError, ValueError, KeyError):
+        return DEFAULT_KAPPA, DEFAULT_LAMBDA
+
+
+def learned_eta(dist, master, kappa=DEFAULT_KAPPA, lam=DEFAULT_LAMBDA, stream=None):
+    """(eta = sigmoid(z)^kappa / (d/dNN)^lam from the network, count of bad outputs)."""
+    from . import mlp_eta, mlp_round
+    eta, bad = mlp_eta(mlp_round(master, stream), dist, stream=stream, kappa=kappa, lam=lam)
+    return eta, int(bad.item())
+
+
+def equal_time_comparison(dists, run_seeds, master, iters=300, alpha=1.0, beta=2.0, rho=0.1,
+                          kappa=DEFAULT_KAPPA, lam=DEFAULT_LAMBDA, verbose=True):
+    """Plain (eta = 1/d, `iters` iterations) against learned eta within the
+    plain arm's wall time, per instance and run seed."""
+    import torch
+
+    from . import Colony
+    rows = []
+    for k, D in enumerate(dists):
+        n = D.shape[0]
+        dev = torch.from_numpy(D).cuda()
+        for seed in run_seeds:
+            col = Colony(dev, alpha, beta, rho, 1.0, n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, L_plain = col.run(n, seed, iters)
+            t_plain = time.perf_counter() - t0
+            col.close()
+            col = Colony(dev, alpha, beta, rho, 1.0, n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eta, bad = learned_eta(dev, master, kappa, lam)
+            active = col.set_eta(eta)
+            torch.cuda.synchronize()
+            t_inf = time.perf_counter() - t0
+            budget = max(1, int((t_plain - t_inf) / (t_plain / iters)))
+            budget = min(budget, iters)
+            _, L_learned = col.run(n, seed, budget)
+            t_learned = time.perf_counter() - t0
+            col.close()
+            gap = (L_plain - L_learned) / L_plain
+            rows.append({"instance": k, "seed": seed, "n": n, "plain_len": L_plain,
+                         "learned_len": L_learned, "gap": gap, "plain_s": t_plain,
+                         "learned_s": t_learned, "inference_s": t_inf,
+                         "learned_iters": budget, "eta_active": bool(active),
+                         "nonfinite": bad})
+            if verbose:
+                print("instance %d seed %d: plain %.4f (%.2f s)  learned %.4f (%.2f s, %d it)  "
+                      "gap %+.2f%%" % (k, seed, L_plain, t_plain, L_learned, t_learned, budget,
+                                       100 * gap), flush=True)
+    return rows
+
+
+def validate_kappa(master, kappas=(0.25, 0.5, 1.0, 2.0), lam=DEFAULT_LAMBDA, count=4,
+                   seeds=(0, 1), iters=300, verbose=True):
+    """Choose kappa on validation instances (clustered n = 2000, instance seeds
+    3000 on, never the evaluation seeds) by the mean relative gap to the plain
+    method over the same iteration count."""
+    import torch
+
+    from . import Colony
+    dists = evaluation_instances(count, seed0=3000)
+    gaps = {k: [] for k in kappas}
+    for D in dists:
+        dev = torch.from_numpy(D).cuda()
+        n = D.shape[0]
+        for seed in seeds:
+            col = Colony(dev, 1.0, 2.0, 0.1, 1.0, n)
+            _, L_plain = col.run(n, seed, iters)
+            col.close()
+            for k in kappas:
+                col = Colony(dev, 1.0, 2.0, 0.1, 1.0, n)
+                eta, _ = learned_eta(dev, master, k, lam)
+                col.set_eta(eta)
+                _, L = col.run(n, seed, iters)
+                col.close()
+                gaps[k].append((L_plain - L) / L_plain)
+    means = {k: float(np.mean(v)) for k, v in gaps.items()}
+    if verbose:
+        for k in kappas:
+            print("validation kappa %.2f: mean gap %+.2f%% over %d runs" % (
+                k, 100 * means[k], len(gaps[k])), flush=True)
+    return max(means, key=means.get), means
+
+
+def evaluation_instances(count=10, n=2000, clusters=30, sigma=0.015, seed0=2000):
+    import aco_instances as inst
+    return [inst.distance_matrix(inst.clustered_cities(n, s, clusters, sigma))
+            for s in range(seed0, seed0 + count)]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["train", "validate", "evaluate"])
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--instances", type=int, default=10)
+    ap.add_argument("--seeds", type=int, default=3)
+    ap.add_argument("--report", default=None)
+    ap.add_argument("--train-iters", type=int, default=300)
+    ap.add_argument("--runs", type=int, default=1)
+    args = ap.parse_args()
+    if args.mode == "train":
+        feats, y = training_set(iters=args.train_iters, runs=args.runs)
+        master, _, curve, secs = train(feats, y, steps=args.steps)
+        save_weights(master, args.out)
+        print("trained in %.1f s; weights -> %s" % (secs, args.out), flush=True)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump({"curve": curve, "seconds": secs, "edges": int(y.numel())}, f)
+    elif args.mode == "validate":
+        master = load_weights(args.weights)
+        assert master is not None, "no weights at " + args.weights
+        kappa, means = validate_kappa(master)
+        with open(args.weights.replace(".npy", ".json"), "w") as f:
+            json.dump({"kappa": kappa, "lambda": DEFAULT_LAMBDA,
+                       "validation_mean_gap": {str(k): v for k, v in means.items()}}, f,
+                      indent=1)
+        print("chose kappa %.2f" % kappa, flush=True)
+    else:
+        master = load_weights(args.weights)
+        assert master is not None, "no weights at " + args.weights
+        kappa, lam = heuristic_config(args.weights)
+        rows = equal_time_comparison(evaluation_instances(args.instances),
+                                     list(range(args.seeds)), master, kappa=kappa, lam=lam)
+        gaps = np.array([r["gap"] for r in rows])
+        print("mean gap %+.2f%% (min %+.2f%%, max %+.2f%%) over %d runs" % (
+            100 * gaps.mean(), 100 * gaps.min(), 100 * gaps.max(), len(rows)), flush=True)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(rows, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,19 +65,21 @@ def test_eta_matches_oracle():
         p = _init_params(seed)
         pb = mlp_round(p).cpu().numpy()
         assert np.array_equal(pb, np.array([oracle.bf16_round(v) for v in p], np.float32))
-        eta, bad = mlp_eta(pb, D)
-        assert int(bad.item()) == 0
-        eta = eta.cpu().numpy().astype(np.float64)
         F = oracle.edge_features(D).reshape(-1, 3)
-        z_o, eta_o = oracle.mlp_forward(pb.astype(np.float64), F, round_bf16=True)
-        z_o = z_o.reshape(n, n)
-        eta_o = eta_o.reshape(n, n)
         off = ~np.eye(n, dtype=bool)
-        assert np.all(np.diag(eta) == 0)
-        # eta' = sigmoid' <= 1/4 of the bound on z
-        tol = 0.25 * 1e-4 * (1 + np.abs(z_o[off])) + 1e-7
-        assert np.all(np.abs(eta[off] - eta_o[off]) <= tol)
-        assert eta_o[off].std() > 1e-3  # the network is not trivially constant
+        for kappa, lam in ((1.0, 0.0), (0.5, 1.0), (2.0, 1.0)):
+            eta, bad = mlp_eta(pb, D, kappa=kappa, lam=lam)
+            assert int(bad.item()) == 0
+            eta = eta.cpu().numpy().astype(np.float64)
+            z_o, eta_o = oracle.mlp_forward(pb.astype(np.float64), F, round_bf16=True,
+                                            kappa=kappa, lam=lam)
+            z_o = z_o.reshape(n, n)
+            eta_o = eta_o.reshape(n, n)
+            assert np.all(np.diag(eta) == 0)
+            # |d log eta / dz| = kappa (1 - sigmoid(z)) <= kappa; one FP32 rounding on top
+            tol = kappa * 1e-4 * (1 + np.abs(z_o[off])) + 2 ** -23
+            assert np.all(np.abs(eta[off] / eta_o[off] - 1) <= tol), (kappa, lam)
+            assert eta_o[off].std() > 1e-3 * eta_o[off].mean()  # not trivially constant
 
 
 def test_gradient_and_adam_match_oracle():
@@ -159,3 +161,24 @@ def test_learned_eta_drives_a_colony_and_nan_falls_back():
     assert int(nbad.item()) > 0
     assert col.set_eta(eta_bad) is False   # falls back to 1/d
     col.close()
+
+
+def test_trained_network_gains_over_plain_at_equal_time():
+    """The committed network (trained on the GPU from plain runs on clustered
+    n = 500 instances) against eta = 1/d on the first two held-out clustered
+    n = 2000 instances (30 Gaussians, sigma 0.015), 300 iterations for the
+    plain arm and the same wall time (inference included) for the learned arm.
+    The gain is a measured effect; this records its sign on a fixed sample."""
+    torch = _torch()
+    from paper_2404_04895_amd import learned
+    master = learned.load_weights()
+    assert master is not None
+    kappa, lam = learned.heuristic_config()
+    rows = learned.equal_time_comparison(learned.evaluation_instances(2), [0], master,
+                                         kappa=kappa, lam=lam, verbose=True)
+    for r in rows:
+        assert r["eta_active"] and r["nonfinite"] == 0
+        assert r["learned_s"] <= 1.05 * r["plain_s"]
+    gaps = [r["gap"] for r in rows]
+    print("gaps", gaps)
+    assert np.mean(gaps) > 0.0

@@ -77,7 +77,15 @@ def test_forward_closed_forms(oracle_lib):
     p[OFF_B3] = 0.75                                 # ... 0.75 is exact in BF16
     z, eta = oracle_lib.mlp_forward(p, feats)
     assert np.all(z == 0.75)
-    assert np.allclose(eta, 1e-4 + (1 - 1e-4) / (1 + math.exp(-0.75)), rtol=1e-15)
+    assert np.allclose(eta, 1 / (1 + math.exp(-0.75)), rtol=1e-15)
+    # eta = sigmoid(z)^kappa / f1^lambda
+    z, eta = oracle_lib.mlp_forward(p, feats, kappa=0.5, lam=1.0)
+    want = (1 / (1 + math.exp(-0.75))) ** 0.5 / feats[:, 0].astype(np.float64)
+    assert np.allclose(eta, want, rtol=1e-14)
+    # far in the tail sigmoid(z) keeps its relative precision (no cancellation)
+    p[OFF_B3] = -60.0
+    z, eta = oracle_lib.mlp_forward(p, feats, kappa=1.0, lam=0.0)
+    assert np.allclose(eta, math.exp(-60.0), rtol=1e-12)
     # one path: z = W3[0] relu(W2[0,0] bf16(relu(W1[0,0] f1)))
     p = _zero_params()
     p[OFF_W1 + 0] = 1.0
