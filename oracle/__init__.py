@@ -62,7 +62,8 @@ def lib():
             "oracle_run": (ctypes.c_int32, [_f32p, _f32p, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_int32,
-                                            ctypes.c_float, ctypes.c_float, ctypes.c_uint64,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                            ctypes.c_uint64,
                                             ctypes.c_uint32, ctypes.c_int32, _f32p, _f32p,
                                             _i32p, _f32p, _i32p, _f32p]),
             "oracle_tsp_exact": (ctypes.c_double, [_f32p, ctypes.c_int32, _i32p]),
@@ -80,6 +81,17 @@ def lib():
             "oracle_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double]),
+            "oracle_roulette_deviate": (ctypes.c_float, [ctypes.c_uint64, ctypes.c_uint32,
+                                                         ctypes.c_uint32, ctypes.c_uint32]),
+            "oracle_select_roulette": (ctypes.c_int32, [_f32p, _u8p, ctypes.c_int32,
+                                                        ctypes.c_uint64, ctypes.c_uint32,
+                                                        ctypes.c_uint32, ctypes.c_uint32]),
+            "oracle_construct_roulette": (None, [_f32p, _f32p, ctypes.c_int32, ctypes.c_uint64,
+                                                 ctypes.c_uint32, _i32p, ctypes.c_int32, _i32p,
+                                                 _f32p]),
+            "oracle_select_roulette_many": (None, [_f32p, _u8p, ctypes.c_int32, ctypes.c_uint64,
+                                                   ctypes.c_uint32, ctypes.c_uint32,
+                                                   ctypes.c_int32, _i32p]),
             "oracle_start_cities": (None, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
                                            ctypes.c_int32, _i32p]),
             "oracle_select_many": (None, [_f32p, _f64p, _u8p, ctypes.c_int32, ctypes.c_double,
@@ -158,17 +170,41 @@ def tour_length(tour, dist):
                                     dist.shape[0])
 
 
-def construct(P, dist, seed, t, ants):
+def construct(P, dist, seed, t, ants, *, selection="adair"):
+    """Tours and lengths of the given ants; selection "adair" (argmax of
+    P * r, Sec. 2.4) or "roulette" (the Roulette Wheel baseline)."""
     n = dist.shape[0]
     P = _c(P, np.float32)
     dist = _c(dist, np.float32)
     ants = _c(ants, np.int32)
     tours = np.zeros((ants.shape[0], n), np.int32)
     lengths = np.zeros(ants.shape[0], np.float32)
-    lib().oracle_construct(_ptr(P, ctypes.c_float), _ptr(dist, ctypes.c_float), n, seed, t,
-                           _ptr(ants, ctypes.c_int32), ants.shape[0],
-                           _ptr(tours, ctypes.c_int32), _ptr(lengths, ctypes.c_float))
+    fn = {"adair": lib().oracle_construct, "roulette": lib().oracle_construct_roulette}[selection]
+    fn(_ptr(P, ctypes.c_float), _ptr(dist, ctypes.c_float), n, seed, t,
+       _ptr(ants, ctypes.c_int32), ants.shape[0], _ptr(tours, ctypes.c_int32),
+       _ptr(lengths, ctypes.c_float))
     return tours, lengths
+
+
+def roulette_deviate(seed, t, a, s):
+    return lib().oracle_roulette_deviate(seed, t, a, s)
+
+
+def select_roulette(row, visited, seed, t, a, s):
+    row = _c(row, np.float32)
+    vis = None if visited is None else _c(visited, np.uint8)
+    return lib().oracle_select_roulette(_ptr(row, ctypes.c_float), _ptr(vis, ctypes.c_uint8),
+                                        row.shape[0], seed, t, a, s)
+
+
+def select_roulette_many(row, visited, seed, t, s, count):
+    """count ants (a = 0..count-1) each take one Roulette Wheel step from the same row."""
+    row = _c(row, np.float32)
+    vis = None if visited is None else _c(visited, np.uint8)
+    out = np.zeros(count, np.int32)
+    lib().oracle_select_roulette_many(_ptr(row, ctypes.c_float), _ptr(vis, ctypes.c_uint8),
+                                      row.shape[0], seed, t, s, count, _ptr(out, ctypes.c_int32))
+    return out
 
 
 def length_lower_bound(dist):
@@ -216,7 +252,8 @@ def gamma(t, T, gamma_max, gamma_min):
 
 
 def run(dist, m, alpha, beta, rho, Q, seed, iters, *, m_max=None, elite_k=0,
-        gamma_max=1.5, gamma_min=1.0, tau0=1.0, iter0=0, eta=None, tau=None):
+        gamma_max=1.5, gamma_min=1.0, tau0=1.0, iter0=0, eta=None, tau=None,
+        selection="adair"):
     """Whole run; returns dict(tau, P, best_tour, best_len, best_iter, S, iter_best)."""
     n = dist.shape[0]
     dist = _c(dist, np.float32)
@@ -232,7 +269,8 @@ def run(dist, m, alpha, beta, rho, Q, seed, iters, *, m_max=None, elite_k=0,
     iter_best = np.zeros(max(iters, 1), np.float32)
     S = lib().oracle_run(_ptr(dist, ctypes.c_float), _ptr(eta_c, ctypes.c_float), n, m,
                          m if m_max is None else m_max, alpha, beta, rho, Q, elite_k,
-                         gamma_max, gamma_min, seed, iter0, iters, _ptr(tau, ctypes.c_float),
+                         gamma_max, gamma_min, {"adair": 0, "roulette": 1}[selection], seed,
+                         iter0, iters, _ptr(tau, ctypes.c_float),
                          _ptr(P, ctypes.c_float), _ptr(best_tour, ctypes.c_int32),
                          ctypes.byref(best_len), ctypes.byref(best_iter),
                          _ptr(iter_best, ctypes.c_float))

@@ -31,7 +31,10 @@
  *   R6  the deposit weight Q/L is quantised to an integer multiple of 2^-S so
  *       that the sum over ants is exact in any order;
  *   R7  gamma follows a cosine annealing schedule from gamma_max to gamma_min
- *       over the run (Sec. 2.4 names the schedule but gives no constants).
+ *       over the run (Sec. 2.4 names the schedule but gives no constants);
+ *   R8  the Roulette Wheel baseline of Sec. 2.4 / Sec. 3 draws one deviate per
+ *       step, word 0 of counter (0, s, a, t), and inverts the cumulative
+ *       distribution of the unvisited cities in ascending city order in FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -187,6 +190,45 @@ ORACLE_API int32_t oracle_select_literal(const double* p, const uint8_t* visited
     return best;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Roulette Wheel (RW) selection: the proportional rule that the IR of      */
+/* Sec. 2.4 replaces and that the ablation of Sec. 3 measures against.      */
+/* City j is drawn with probability p_j / sum of p_k over the unvisited k,  */
+/* p being the row of M_p (Eq. 1; gamma = 1 gives it exactly).  Reading R8: */
+/* one deviate v per step, x = v * total, and the first unvisited city in   */
+/* ascending order whose running FP64 sum exceeds x.  A city of weight 0 is */
+/* never drawn; if every unvisited city has weight 0, the smallest one is   */
+/* taken (the same fallback as the argmax rule's tie-break).                */
+/* ------------------------------------------------------------------------ */
+ORACLE_API float oracle_roulette_deviate(uint64_t seed, uint32_t t, uint32_t a, uint32_t s) {
+    uint32_t key[2], ctr[4] = {0u, s, a, t}, out[4];
+    seed_to_key(seed, key);
+    oracle_philox4x32_10(ctr, key, out);
+    return oracle_to_unit(out[0]);
+}
+
+ORACLE_API int32_t oracle_select_roulette(const float* row, const uint8_t* visited, int32_t n,
+                                          uint64_t seed, uint32_t t, uint32_t a, uint32_t s) {
+    double total = 0.0;
+    int32_t first_free = -1;
+    for (int32_t j = 0; j < n; ++j) {
+        if (visited && visited[j]) continue;
+        if (first_free < 0) first_free = j;
+        total += (double)row[j];
+    }
+    if (!(total > 0.0)) return first_free;
+    double x = (double)oracle_roulette_deviate(seed, t, a, s) * total;
+    double running = 0.0;
+    int32_t last_positive = first_free;
+    for (int32_t j = 0; j < n; ++j) {
+        if (visited && visited[j]) continue;
+        running += (double)row[j];
+        if (row[j] > 0.0f) last_positive = j;
+        if (running > x) return j;
+    }
+    return last_positive; /* not reached: x < total and the running sum ends at total */
+}
+
 /* Fitness f of Eq. (3) (reading R4): closed tour length, summed in FP64 in
  * tour order (closing edge last) and rounded once to FP32. */
 ORACLE_API float oracle_tour_length(const int32_t* tour, const float* dist, int32_t n) {
@@ -199,12 +241,13 @@ ORACLE_API float oracle_tour_length(const int32_t* tour, const float* dist, int3
 }
 
 /* Tensorization of the ant system, Sec. 2.2, as the function it maps over
- * ants: ant a starts at its random city and takes n-1 selections (Sec. 2.4)
- * from the shared P.  Ants are independent, so they run in parallel.
- * tours is count x n, lengths is count. */
-ORACLE_API void oracle_construct(const float* P, const float* dist, int32_t n,
-                                 uint64_t seed, uint32_t t, const int32_t* ants,
-                                 int32_t count, int32_t* tours, float* lengths) {
+ * ants: ant a starts at its random city and takes n-1 selections (Sec. 2.4,
+ * or the Roulette Wheel when roulette != 0) from the shared P.  Ants are
+ * independent, so they run in parallel.  tours is count x n, lengths is
+ * count. */
+static void construct_ants(const float* P, const float* dist, int32_t n, uint64_t seed,
+                           uint32_t t, const int32_t* ants, int32_t count, int32_t roulette,
+                           int32_t* tours, float* lengths) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t idx = 0; idx < count; ++idx) {
         uint32_t a = (uint32_t)ants[idx];
@@ -214,13 +257,27 @@ ORACLE_API void oracle_construct(const float* P, const float* dist, int32_t n,
         tour[0] = c;
         visited[c] = 1;
         for (int32_t s = 1; s < n; ++s) {
-            c = oracle_select(P + (size_t)c * (size_t)n, visited, n, seed, t, a, (uint32_t)s);
+            const float* row = P + (size_t)c * (size_t)n;
+            c = roulette ? oracle_select_roulette(row, visited, n, seed, t, a, (uint32_t)s)
+                         : oracle_select(row, visited, n, seed, t, a, (uint32_t)s);
             tour[s] = c;
             visited[c] = 1;
         }
         lengths[idx] = oracle_tour_length(tour, dist, n);
         free(visited);
     }
+}
+
+ORACLE_API void oracle_construct(const float* P, const float* dist, int32_t n,
+                                 uint64_t seed, uint32_t t, const int32_t* ants,
+                                 int32_t count, int32_t* tours, float* lengths) {
+    construct_ants(P, dist, n, seed, t, ants, count, 0, tours, lengths);
+}
+
+ORACLE_API void oracle_construct_roulette(const float* P, const float* dist, int32_t n,
+                                          uint64_t seed, uint32_t t, const int32_t* ants,
+                                          int32_t count, int32_t* tours, float* lengths) {
+    construct_ants(P, dist, n, seed, t, ants, count, 1, tours, lengths);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -342,11 +399,13 @@ ORACLE_API float oracle_gamma(int32_t t, int32_t T, float gamma_max, float gamma
  * constructs (Sec. 2.2, 2.4), the best-so-far is kept (smallest length, ties
  * to the earlier iteration then the smaller ant), the elite deposit
  * (Sec. 2.3) and evaporation update tau, and P is rebuilt with gamma_{t+1}
- * (Sec. 2.1).  tau (n x n) is in/out; P (n x n) is out. */
+ * (Sec. 2.1).  roulette != 0 selects by the Roulette Wheel instead of AdaIR.
+ * tau (n x n) is in/out; P (n x n) is out. */
 ORACLE_API int32_t oracle_run(const float* dist, const float* eta, int32_t n, int32_t m,
                               int32_t m_max, float alpha, float beta, float rho, float Q,
                               int32_t elite_k, float gamma_max, float gamma_min,
-                              uint64_t seed, uint32_t iter0, int32_t iters, float* tau,
+                              int32_t roulette, uint64_t seed, uint32_t iter0, int32_t iters,
+                              float* tau,
                               float* P, int32_t* best_tour, float* best_len,
                               int32_t* best_iter, float* iter_best_len) {
     size_t nn = (size_t)n * (size_t)n;
@@ -367,7 +426,7 @@ ORACLE_API int32_t oracle_run(const float* dist, const float* eta, int32_t n, in
                       oracle_gamma(0, iters, gamma_max, gamma_min), P);
     for (int32_t it = 0; it < iters; ++it) {
         uint32_t t = iter0 + (uint32_t)it;
-        oracle_construct(P, dist, n, seed, t, ants, m, tours, lengths);
+        construct_ants(P, dist, n, seed, t, ants, m, roulette, tours, lengths);
         float round_best = INFINITY;
         int32_t round_ant = -1;
         for (int32_t a = 0; a < m; ++a) {
@@ -475,4 +534,14 @@ ORACLE_API void oracle_select_many(const float* row, const double* p, const uint
         out[a] = literal ? oracle_select_literal(p, visited, n, gamma, seed, t, (uint32_t)a, s)
                          : oracle_select(row, visited, n, seed, t, (uint32_t)a, s);
     }
+}
+
+/* One Roulette Wheel step for each of `count` ants a = 0..count-1 at step s
+ * from the same row and visited set. */
+ORACLE_API void oracle_select_roulette_many(const float* row, const uint8_t* visited, int32_t n,
+                                            uint64_t seed, uint32_t t, uint32_t s,
+                                            int32_t count, int32_t* out) {
+#pragma omp parallel for schedule(static)
+    for (int32_t a = 0; a < count; ++a)
+        out[a] = oracle_select_roulette(row, visited, n, seed, t, (uint32_t)a, s);
 }
