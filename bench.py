@@ -223,6 +223,10 @@ def main():
     ap.add_argument("--workload", default="clustered-n5000-m5000")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--selection", default="adair", choices=["adair", "adair-sorted", "roulette"],
+                    help="per-step selection rule of the construct")
+    ap.add_argument("--walk", type=int, default=None,
+                    help="sorted batches per step before the scan (adair-sorted)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a "
                          "reference for HBM byte counters)")
@@ -251,6 +255,9 @@ def main():
     torch.cuda.set_device(dev)
     col = Colony(torch.from_numpy(D).to(dev), w.alpha, w.beta, w.rho, w.Q, m, tau0=w.tau0,
                  elite_k=w.elite_k, gamma_max=w.gamma_max, gamma_min=w.gamma_min)
+    col.set_selection(args.selection)
+    if args.walk is not None:
+        col.set_sorted_walk(args.walk)
     stream = torch.cuda.current_stream()
 
     def step(t, ev=None):
@@ -308,7 +315,8 @@ def main():
         "config": {"workload": w.name, "n": n, "m": m, "alpha": w.alpha, "beta": w.beta,
                    "rho": w.rho, "Q": w.Q, "cities": "%s, %d Gaussians sigma %g" % (
                        w.family, w.clusters, w.sigma) if w.family != "uniform" else "uniform",
-                   "gamma": [w.gamma_max, w.gamma_min], "seed": args.seed},
+                   "gamma": [w.gamma_max, w.gamma_min], "seed": args.seed,
+                   "selection": args.selection},
         "roofline": {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": bytes_launch,

@@ -166,6 +166,17 @@ const float* aco_pheromone(const aco_ctx* ctx);
 const float* aco_transition_matrix(const aco_ctx* ctx);
 const int32_t* aco_tours(const aco_ctx* ctx);
 const float* aco_lengths(const aco_ctx* ctx);
+/* The rows of P sorted by the last construct under ACO_SELECT_ADAIR_SORTED,
+ * n x ld: values (FP32, descending within a row) and their cities (uint16);
+ * the first n entries of each row are meaningful. */
+const float* aco_sorted_rows(const aco_ctx* ctx);
+const uint16_t* aco_sorted_cities(const aco_ctx* ctx);
+
+/* What the last ACO_SELECT_ADAIR_SORTED construct read (blocks): out3[0] the
+ * batches of 64 sorted entries read, summed over ants and steps; out3[1] the
+ * steps the walk left to the scan; out3[2] the live 4-city blocks those scans
+ * read.  Errors: ACO_EINVAL for a NULL pointer. */
+aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3);
 
 /* Exponent S of the deposit quantisation: the largest S with
  * m_max * Q / L_lb * 2^S < 2^62, L_lb = sum over cities of the nearest
@@ -199,6 +210,51 @@ aco_status aco_set_state(aco_ctx* ctx, const float* tau_dev, uint32_t iter);
 /* Select the construct schedule of this context (ACO_SCHED_*).
  * Errors: ACO_EINVAL for an unknown code. */
 aco_status aco_set_schedule(aco_ctx* ctx, int32_t schedule);
+
+/* Per-step selection rule of aco_construct (and so of aco_run).
+ *   ACO_SELECT_ADAIR     Sec. 2.4: argmax over the unvisited j of fl32(P[c,j] * r_j),
+ *                        r_j the deviate of counter (j/4, s, ant, iter), word j mod 4
+ *                        (the default).
+ *   ACO_SELECT_ROULETTE  the Roulette Wheel that Sec. 2.4's Independent Roulette
+ *                        replaces (the baseline of the ablation in Sec. 3): city j
+ *                        with probability P[c,j] / sum of P[c,k] over the unvisited
+ *                        k.  One deviate per step, v = word 0 of counter
+ *                        (0, s, ant, iter); x = v * total; the first city in
+ *                        ascending order of positive weight whose running sum
+ *                        exceeds x.  Sums in FP64, associated per chunk of
+ *                        4 * lanes cities, so the city can differ from a strictly
+ *                        sequential sum's only when x lies within rounding of a
+ *                        boundary.  No positive weight left: the smallest unvisited
+ *                        city.  The paper's RW samples from M_p of Eq. (1), i.e.
+ *                        P built with gamma = 1 (aco_set_params with gamma_max =
+ *                        gamma_min = 1 for aco_run).  The row's chunk totals are
+ *                        kept one per lane, so a forced schedule of G lanes needs
+ *                        ceil(ceil(n/4)/G) <= G (16 lanes: n <= 1024; 32: n <= 4096);
+ *                        ACO_SCHED_AUTO always fits.
+ * Errors: ACO_EINVAL for an unknown code; aco_construct returns ACO_EINVAL when
+ * the schedule does not fit the roulette wheel at this n. */
+#define ACO_SELECT_ADAIR 0
+#define ACO_SELECT_ROULETTE 1
+#define ACO_SELECT_ADAIR_SORTED 2
+aco_status aco_set_selection(aco_ctx* ctx, int32_t selection);
+
+/* ACO_SELECT_ADAIR_SORTED: the same selection as ACO_SELECT_ADAIR, bit for bit,
+ * found with less work.  Every deviate of Sec. 2.4 is below 1, so a city's
+ * score fl32(P[c,j] * r_j) never exceeds P[c,j].  aco_construct first sorts
+ * every row of P (value descending, city ascending; into workspace buffers).
+ * A step then reads the row's entries in that order, 64 at a time, scoring
+ * the unvisited ones.  It stops as soon as the smallest P of a batch is below
+ * the best score found: no later city can reach that score.  If `batches`
+ * batches (aco_set_sorted_walk) have not decided the step, it scans the live
+ * blocks as ACO_SELECT_ADAIR does.  Runs on ACO_SCHED_G64_LIVE (chosen by
+ * ACO_SCHED_AUTO; another forced schedule makes aco_construct return
+ * ACO_EINVAL). */
+#define ACO_SORTED_WALK_MAX 256
+
+/* Batches of 64 sorted entries a step of ACO_SELECT_ADAIR_SORTED reads before
+ * it falls back to the scan (default 2; 0 always scans).
+ * Errors: ACO_EINVAL outside [0, ACO_SORTED_WALK_MAX]. */
+aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches);
 
 /* ------------------------------------------------------------------------ */
 /* Batched engine: many independent instances of uneven size advanced        */

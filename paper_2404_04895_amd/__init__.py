@@ -141,6 +141,33 @@ class Colony:
     def set_schedule(self, schedule: int):
         check(lib().aco_set_schedule(self._ctx, schedule), "aco_set_schedule")
 
+    def set_selection(self, selection: str):
+        """"adair" (argmax of P * r, the default), "adair-sorted" (the same
+        selection, bit for bit, by a walk of each row sorted by P) or
+        "roulette" (the Roulette Wheel baseline: city j with probability
+        P[c,j] over the unvisited sum)."""
+        code = {"adair": _native.SELECT_ADAIR, "roulette": _native.SELECT_ROULETTE,
+                "adair-sorted": _native.SELECT_ADAIR_SORTED}[selection]
+        check(lib().aco_set_selection(self._ctx, code), "aco_set_selection")
+
+    def set_sorted_walk(self, batches: int):
+        """Batches of 64 sorted entries a step reads before it scans (adair-sorted)."""
+        check(lib().aco_set_sorted_walk(self._ctx, batches), "aco_set_sorted_walk")
+
+    def sorted_walk_stats(self):
+        """(batches read, steps scanned, blocks scanned) of the last adair-sorted construct."""
+        out = np.zeros(3, np.uint64)
+        check(lib().aco_sorted_walk_stats(self._ctx, out.ctypes.data_as(ctypes.c_void_p)),
+              "aco_sorted_walk_stats")
+        return tuple(int(v) for v in out)
+
+    def sorted_rows(self):
+        """(values, cities) of the rows of P sorted by the last adair-sorted construct."""
+        torch = _torch()
+        Ps = self._view(lib().aco_sorted_rows(self._ctx), torch.float32, (self.n, self.ld))
+        Js = self._view(lib().aco_sorted_cities(self._ctx), torch.int16, (self.n, self.ld))
+        return Ps[:, :self.n], Js[:, :self.n]
+
     def set_stream(self, stream):
         self._stream = stream
         check(lib().aco_set_stream(self._ctx, _stream_handle(stream)), "aco_set_stream")

@@ -36,6 +36,7 @@ class BatchView(ctypes.Structure):
 SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE = -1, 0, 1, 2, 3, 4
 SCHEDULES = (SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE)
 BATCH_GRAPH, BATCH_TIME_CONSTRUCT = 1, 2
+SELECT_ADAIR, SELECT_ROULETTE, SELECT_ADAIR_SORTED = 0, 1, 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -59,6 +60,9 @@ SIGNATURES = {
     "aco_gamma_schedule": (_f32, [_i32, _i32, _f32, _f32]),
     "aco_pheromone": (_vp, [_vp]),
     "aco_transition_matrix": (_vp, [_vp]),
+    "aco_sorted_rows": (_vp, [_vp]),
+    "aco_sorted_cities": (_vp, [_vp]),
+    "aco_sorted_walk_stats": (_i32, [_vp, _vp]),
     "aco_tours": (_vp, [_vp]),
     "aco_lengths": (_vp, [_vp]),
     "aco_deposit_scale": (_i32, [_vp]),
@@ -67,6 +71,8 @@ SIGNATURES = {
     "aco_set_state": (_i32, [_vp, _vp, _u32]),
     "aco_uniforms": (_i32, [_u64, _u32, _u32, _u32, _i32, _vp, _vp]),
     "aco_set_schedule": (_i32, [_vp, _i32]),
+    "aco_set_selection": (_i32, [_vp, _i32]),
+    "aco_set_sorted_walk": (_i32, [_vp, _i32]),
     "aco_batch_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, _i32]),
     "aco_batch_create": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp, _vp,
                                 ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaco.so")
-SOURCES = ["api.hip", "batch_api.hip", "construct.hip", "update.hip", "learned.hip",
-           "learned_api.hip"]
+SOURCES = ["api.hip", "batch_api.hip", "construct.hip", "sorted.hip", "update.hip",
+           "learned.hip", "learned_api.hip"]
 ARCH = os.environ.get("ACO_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

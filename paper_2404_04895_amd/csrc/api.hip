@@ -28,6 +28,8 @@ struct aco_ctx {
     uint32_t last_iter = 0;
     uint32_t iter = 0;         // running iteration counter used by aco_run
     int32_t schedule = -1;     // construct schedule (ACO_SCHED_*), -1: by size
+    int32_t selection = ACO_SELECT_ADAIR;  // per-step selection rule (ACO_SELECT_*)
+    int32_t walk = 2;          // sorted batches a step reads before the scan
 };
 
 namespace {
@@ -113,6 +115,9 @@ Layout make_layout(int32_t n, int32_t ld, int32_t m_max) {
     L.off_row_min = take(sizeof(float) * static_cast<size_t>(n));
     L.off_lower_bound = take(sizeof(double));
     L.off_flags = take(sizeof(uint32_t) * 4);
+    L.off_Ps = take(mat);
+    L.off_Js = take(sizeof(uint16_t) * static_cast<size_t>(n) * ld);
+    L.off_walk_stats = take(sizeof(unsigned long long) * 3);
     L.total = off;
     return L;
 }
@@ -133,6 +138,9 @@ Buffers carve(char* base, const Layout& L) {
     B.row_min = reinterpret_cast<float*>(base + L.off_row_min);
     B.lower_bound = reinterpret_cast<double*>(base + L.off_lower_bound);
     B.flags = reinterpret_cast<uint32_t*>(base + L.off_flags);
+    B.Ps = reinterpret_cast<float*>(base + L.off_Ps);
+    B.Js = reinterpret_cast<uint16_t*>(base + L.off_Js);
+    B.walk_stats = reinterpret_cast<unsigned long long*>(base + L.off_walk_stats);
     return B;
 }
 
@@ -295,6 +303,24 @@ aco_status aco_set_schedule(aco_ctx* ctx, int32_t schedule) {
     return ACO_OK;
 }
 
+aco_status aco_set_selection(aco_ctx* ctx, int32_t selection) {
+    if (aco_status st = check_ctx(ctx)) return st;
+    if (selection != ACO_SELECT_ADAIR && selection != ACO_SELECT_ROULETTE &&
+        selection != ACO_SELECT_ADAIR_SORTED)
+        return fail(ACO_EINVAL, "aco_set_selection: unknown selection %d", selection);
+    ctx->selection = selection;
+    return ACO_OK;
+}
+
+aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches) {
+    if (aco_status st = check_ctx(ctx)) return st;
+    if (batches < 0 || batches > ACO_SORTED_WALK_MAX)
+        return fail(ACO_EINVAL, "aco_set_sorted_walk: %d outside [0, %d]", batches,
+                    ACO_SORTED_WALK_MAX);
+    ctx->walk = batches;
+    return ACO_OK;
+}
+
 aco_status aco_transition(aco_ctx* ctx, float gamma) {
     if (aco_status st = check_ctx(ctx)) return st;
     if (!finite_positive(gamma)) return fail(ACO_EINVAL, "aco_transition: gamma <= 0");
@@ -312,9 +338,24 @@ aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) 
         return fail(ACO_EINVAL, "aco_construct: m = %d outside [1, %d]", m, ctx->m_max);
     if (!ctx->have_P) return fail(ACO_ESTATE, "aco_construct: no transition matrix yet");
     if (aco_status st = bind_device(ctx)) return st;
-    const int32_t sched = ctx->schedule >= 0 ? ctx->schedule : aco::default_schedule(ctx->n);
+    const bool sorted = ctx->selection == ACO_SELECT_ADAIR_SORTED;
+    int32_t sched = ctx->schedule >= 0 ? ctx->schedule : aco::default_schedule(ctx->n);
+    if (sorted) {
+        if (ctx->schedule >= 0 && ctx->schedule != ACO_SCHED_G64_LIVE)
+            return fail(ACO_EINVAL,
+                        "aco_construct: the sorted walk runs on ACO_SCHED_G64_LIVE only");
+        sched = ACO_SCHED_G64_LIVE;
+    }
+    if (ctx->selection == ACO_SELECT_ROULETTE && !aco::roulette_fits(ctx->n, sched))
+        return fail(ACO_EINVAL,
+                    "aco_construct: schedule %d cannot run the roulette wheel at n = %d", sched,
+                    ctx->n);
+    if (sorted)
+        ACO_HIP(aco::launch_sort_rows(ctx->buf.P, ctx->n, ctx->ld, ctx->buf.Ps, ctx->buf.Js,
+                                      ctx->buf.walk_stats, ctx->stream),
+                "sort rows");
     ACO_HIP(aco::launch_construct(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, seed, iter, sched,
-                                  ctx->stream),
+                                  ctx->selection, ctx->walk, ctx->stream),
             "construct");
     ctx->have_tours = true;
     ctx->last_m = m;
@@ -361,6 +402,20 @@ aco_status aco_run(aco_ctx* ctx, int32_t m, uint64_t seed, int32_t iters,
 
 const float* aco_pheromone(const aco_ctx* ctx) { return ctx ? ctx->buf.tau : nullptr; }
 const float* aco_transition_matrix(const aco_ctx* ctx) { return ctx ? ctx->buf.P : nullptr; }
+aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3) {
+    if (aco_status st = check_ctx(ctx)) return st;
+    if (!out3) return fail(ACO_EINVAL, "aco_sorted_walk_stats: out is NULL");
+    if (aco_status st = bind_device(ctx)) return st;
+    unsigned long long v[3] = {0, 0, 0};
+    ACO_HIP(hipMemcpyAsync(v, ctx->buf.walk_stats, sizeof(v), hipMemcpyDeviceToHost, ctx->stream),
+            "walk stats");
+    ACO_HIP(hipStreamSynchronize(ctx->stream), "walk stats (sync)");
+    for (int k = 0; k < 3; ++k) out3[k] = static_cast<uint64_t>(v[k]);
+    return ACO_OK;
+}
+
+const float* aco_sorted_rows(const aco_ctx* ctx) { return ctx ? ctx->buf.Ps : nullptr; }
+const uint16_t* aco_sorted_cities(const aco_ctx* ctx) { return ctx ? ctx->buf.Js : nullptr; }
 const int32_t* aco_tours(const aco_ctx* ctx) { return ctx ? ctx->buf.tours : nullptr; }
 const float* aco_lengths(const aco_ctx* ctx) { return ctx ? ctx->buf.lengths : nullptr; }
 int32_t aco_deposit_scale(const aco_ctx* ctx) { return ctx ? ctx->S : -1; }

@@ -26,7 +26,7 @@ size_t align256(size_t x) { return aco::align_up(x, 256); }
 int32_t batch_ld(int32_t n) { return (n + 31) / 32 * 32; }  // 128-byte rows
 
 struct BatchLayout {
-    size_t insts, tasks, rows, queue, state, gammas, dist, tau, P, tours, lengths, succ, pred,
+    size_t insts, tasks, queue_start, rows, queue, state, gammas, dist, tau, P, tours, lengths, succ, pred,
         weight, best_tour, best, row_min, lower, flags, total;
     int64_t mat_elems, tour_elems, succ_elems, ant_elems, city_elems;
     int32_t max_task_count, nrows;
@@ -52,8 +52,9 @@ BatchLayout make_batch_layout(const int32_t* n, const int32_t* m, int32_t count)
     };
     L.insts = take(sizeof(aco::BatchInstance) * count);
     L.tasks = take(sizeof(aco::BatchTask) * L.max_task_count);
+    L.queue_start = take(sizeof(int32_t) * (aco::kQueues + 1));
     L.rows = take(sizeof(aco::RowTask) * L.nrows);
-    L.queue = take(sizeof(uint32_t));
+    L.queue = take(sizeof(uint32_t) * aco::kQueues);
     L.state = take(sizeof(aco::IterState));
     L.gammas = take(sizeof(float) * (kMaxRunIters + 1));
     L.dist = take(sizeof(float) * L.mat_elems);
@@ -114,24 +115,40 @@ int32_t pick_schedule(const aco_batch* b, int32_t n) {
     return aco::default_schedule(n);
 }
 
-// Rebuild the construct task queue (largest instance first) for the current
-// schedule table and upload it.
+// Rebuild the construct task queues for the current schedule table and
+// upload them.  Instances go, largest first, to the queue with the least work
+// so far (work = ant-steps times row length, m (n - 1) n); within a queue the
+// tasks keep that order.
 aco_status upload_tasks(aco_batch* b) {
-    std::vector<aco::BatchTask> tasks;
+    std::vector<std::vector<aco::BatchTask>> per(aco::kQueues);
+    std::vector<double> load(aco::kQueues, 0.0);
     size_t lds = 0;
     for (int32_t i : b->order) {
         const aco::BatchInstance& in = b->insts[i];
         const int32_t sched = pick_schedule(b, in.n);
         const int32_t per_wave = 64 / aco::schedule_lanes(sched);
+        const int32_t q = static_cast<int32_t>(
+            std::min_element(load.begin(), load.end()) - load.begin());
         for (int32_t a = 0; a < in.m; a += per_wave)
-            tasks.push_back(aco::BatchTask{i, a, std::min(per_wave, in.m - a), sched});
+            per[q].push_back(aco::BatchTask{i, a, std::min(per_wave, in.m - a), sched});
+        load[q] += static_cast<double>(in.m) * (in.n - 1) * in.n;
         lds = std::max(lds, aco::wave_lds_bytes(in.n, sched));
     }
+    std::vector<aco::BatchTask> tasks;
+    std::vector<int32_t> start(aco::kQueues + 1, 0);
+    for (int32_t q = 0; q < aco::kQueues; ++q) {
+        start[q] = static_cast<int32_t>(tasks.size());
+        tasks.insert(tasks.end(), per[q].begin(), per[q].end());
+    }
+    start[aco::kQueues] = static_cast<int32_t>(tasks.size());
     if (static_cast<int32_t>(tasks.size()) > b->layout.max_task_count)
         return fail(ACO_EINVAL, "batch: task table overflow");
     ACO_HIP(hipMemcpyAsync(b->dev.tasks, tasks.data(), sizeof(aco::BatchTask) * tasks.size(),
                            hipMemcpyHostToDevice, b->stream),
             "upload tasks");
+    ACO_HIP(hipMemcpyAsync(b->dev.queue_start, start.data(), sizeof(int32_t) * start.size(),
+                           hipMemcpyHostToDevice, b->stream),
+            "upload queue starts");
     ACO_HIP(hipStreamSynchronize(b->stream), "upload tasks (sync)");
     b->ntasks = static_cast<int32_t>(tasks.size());
     b->task_lds = lds;
@@ -240,6 +257,7 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
     char* w = b->ws;
     b->dev.insts = reinterpret_cast<aco::BatchInstance*>(w + L.insts);
     b->dev.tasks = reinterpret_cast<aco::BatchTask*>(w + L.tasks);
+    b->dev.queue_start = reinterpret_cast<int32_t*>(w + L.queue_start);
     b->dev.rows = reinterpret_cast<aco::RowTask*>(w + L.rows);
     b->dev.queue = reinterpret_cast<uint32_t*>(w + L.queue);
     b->dev.state = reinterpret_cast<aco::IterState*>(w + L.state);

@@ -15,6 +15,11 @@
 // generator is keyed by block index, not list position or lane, so the group
 // width and the list change no result.
 //
+// The Roulette Wheel baseline (the proportional rule that IR replaces; the
+// ablation of Sec. 3) runs in the same skeleton with another per-step
+// selection: the inverse of the cumulative distribution of the unvisited
+// cities in ascending order, in FP64, with one deviate per step.
+//
 // Outputs per ant: the tour (m x n int32), its closed length (FP64 sum in
 // tour order, rounded once to FP32 -- the fitness f of Eq. (3)), and the
 // successor / predecessor of every city, stored city-major so that the
@@ -91,12 +96,230 @@ __device__ __forceinline__ int32_t group_uniform(int32_t v) {
     return v;
 }
 
+// ---- roulette wheel helpers ----------------------------------------------
+
+__device__ __forceinline__ double f64_from_halves(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+__device__ __forceinline__ uint32_t f64_lo(double v) {
+    return static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(v)));
+}
+
+__device__ __forceinline__ uint32_t f64_hi(double v) {
+    return static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(v)) >> 32);
+}
+
+// v from the lane CTRL names within the 16-lane row; lanes without a source
+// in the row get +0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint32_t lo = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(f64_lo(v)), CTRL, 0xF, 0xF, false));
+    const uint32_t hi = static_cast<uint32_t>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(f64_hi(v)), CTRL, 0xF, 0xF, false));
+    return f64_from_halves(lo, hi);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int32_t lane) {
+    const uint32_t lo =
+        static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(f64_lo(v)), lane));
+    const uint32_t hi =
+        static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(f64_hi(v)), lane));
+    return f64_from_halves(lo, hi);
+}
+
+// Inclusive prefix sum over the G lanes of a group, in a fixed association:
+// shifts by 1, 2, 4, 8 within each 16-lane row, then the row totals.
+template <int G>
+__device__ __forceinline__ double group_scan_f64(double v) {
+    v += dpp_f64<0x111>(v);  // row_shr:1
+    v += dpp_f64<0x112>(v);  // row_shr:2
+    v += dpp_f64<0x114>(v);  // row_shr:4
+    v += dpp_f64<0x118>(v);  // row_shr:8
+    const int32_t lane = threadIdx.x & (kWave - 1);
+    if constexpr (G >= 32) {
+        const double r15 = readlane_f64(v, 15);
+        const double r47 = readlane_f64(v, 47);
+        if ((lane & 31) >= 16) v += (lane < 32) ? r15 : r47;
+    }
+    if constexpr (G == 64) {
+        const double r31 = readlane_f64(v, 31);
+        if (lane >= 32) v += r31;
+    }
+    return v;
+}
+
+// The value of the group's last lane, on every lane of the group.
+template <int G>
+__device__ __forceinline__ double group_last_f64(double v) {
+    if constexpr (G == 64) {
+        return readlane_f64(v, 63);
+    } else {
+        const int32_t g = (threadIdx.x & (kWave - 1)) / G;
+        double r = 0.0;
+#pragma unroll
+        for (int32_t k = 0; k < kWave / G; ++k) {
+            const double t = readlane_f64(v, k * G + G - 1);
+            if (g == k) r = t;
+        }
+        return r;
+    }
+}
+
+// Block b of the row with the visited cities' weights set to +0.
+__device__ __forceinline__ float4 masked_block(const float* row, const uint32_t* visited,
+                                               int32_t b) {
+    float4 p = *reinterpret_cast<const float4*>(row + 4 * b);
+    const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
+    p.x = (taken & 1u) ? 0.0f : p.x;
+    p.y = (taken & 2u) ? 0.0f : p.y;
+    p.z = (taken & 4u) ? 0.0f : p.z;
+    p.w = (taken & 8u) ? 0.0f : p.w;
+    return p;
+}
+
+// Weight of a block: its four entries summed in city order in FP64.
+__device__ __forceinline__ double block_weight(float4 p) {
+    return ((static_cast<double>(p.x) + static_cast<double>(p.y)) + static_cast<double>(p.z)) +
+           static_cast<double>(p.w);
+}
+
+// One Roulette Wheel step of group g: city j with probability P[c,j] over
+// the sum of P[c,k] for the unvisited k.  Pass 1 streams the live blocks in
+// ascending order, G blocks (one chunk) at a time; lane k of the group keeps
+// the running total before and after chunk k (nblk <= G*G is required).
+// The deviate of counter (0, s, ant, iter) sets x = v * total; pass 2
+// re-reads the first chunk whose closing total exceeds x and takes the first
+// city of positive weight whose running sum exceeds x.  All sums are FP64;
+// they are associated per chunk rather than strictly left to right, so a
+// different city than a sequential sum's can only come from an x within
+// rounding of a boundary.  With no positive weight left, the smallest
+// unvisited city is taken.
+template <int G, bool LIVE>
+__device__ __forceinline__ int32_t roulette_select(const InstanceView& I, const float* row,
+                                                   const uint32_t* visited,
+                                                   const uint16_t* live, int32_t span,
+                                                   int32_t gl, int32_t g, int32_t s,
+                                                   int32_t ant) {
+    double run = 0.0;
+    double chunk_lo = 0.0;
+    double chunk_hi = 0.0;
+    int32_t nchunks = 0;
+    for (int32_t base = 0; base < span; base += G, ++nchunks) {
+        const int32_t pos = base + gl;
+        double w = 0.0;
+        if (pos < span) w = block_weight(masked_block(row, visited, LIVE ? live[pos] : pos));
+        const double total = group_last_f64<G>(group_scan_f64<G>(w));
+        if (gl == nchunks) chunk_lo = run;
+        run += total;
+        if (gl == nchunks) chunk_hi = run;
+    }
+    // the smallest unvisited city (one exists: fewer than n cities are taken)
+    auto smallest_free = [&]() {
+        int32_t first = 0x7FFFFFFF;
+        for (int32_t base = 0; base < span; base += G) {
+            const int32_t pos = base + gl;
+            if (pos < span) {
+                const int32_t b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
+                const uint32_t free = ~(visited[b >> 3] >> ((b & 7) << 2)) & 0xFu;
+                if (free) first = min(first, 4 * b + __builtin_ctz(free));
+            }
+        }
+        return group_reduce<G, false>(first);
+    };
+    if (!(run > 0.0)) return smallest_free();
+    const PhiloxOut d = philox10(0u, static_cast<uint32_t>(s), static_cast<uint32_t>(ant), I.iter,
+                                 I.key0, I.key1);
+    const double x = static_cast<double>(unit_from_word(d.w0)) * run;
+    // x < run (the deviate is below 1), so the last chunk's closing total
+    // exceeds it; the guard below only keeps C in range
+    const uint64_t group_bits = (G == 64) ? ~0ull : ((1ull << (G & 63)) - 1ull);
+    const uint64_t over = (__ballot(gl < nchunks && chunk_hi > x) >> (g * G)) & group_bits;
+    const int32_t C = over ? __builtin_ctzll(over) : nchunks - 1;
+    const double lo = __shfl(chunk_lo, g * G + C);
+    const int32_t pos = C * G + gl;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int32_t b = 0;
+    if (pos < span) {
+        b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
+        p = masked_block(row, visited, b);
+    }
+    const double incl = group_scan_f64<G>(block_weight(p));
+    double excl = __shfl_up(incl, 1, G);
+    if (gl == 0) excl = 0.0;
+    int32_t pick = 0x7FFFFFFF;
+    int32_t last = -1;
+    if (pos < span) {
+        const float q[4] = {p.x, p.y, p.z, p.w};
+        double acc = 0.0;
+#pragma unroll
+        for (int32_t k = 0; k < 4; ++k) {
+            acc = (k == 0) ? static_cast<double>(q[0]) : acc + static_cast<double>(q[k]);
+            const bool positive = __float_as_uint(q[k]) != 0u;
+            if (positive) last = 4 * b + k;
+            if (pick == 0x7FFFFFFF && positive && lo + (excl + acc) > x) pick = 4 * b + k;
+        }
+    }
+    pick = group_reduce<G, false>(pick);
+    // rounding can leave x past the last running sum of the chunk: its last
+    // city of positive weight then takes the draw (the chunk has one)
+    if (pick == 0x7FFFFFFF) pick = group_reduce<G, true>(last);
+    if (pick < 0) pick = smallest_free();
+    return pick;
+}
+
 // Build the tours of up to 64/G ants of one instance: group g of this wave
 // builds ant ant0 + g if g < nants.  `lds` is this wave's LDS region of
 // (64/G) * group_lds_words(n, LIVE) words.
-template <int G, bool LIVE>
+// Sorted walk of one step (G = 64): read the row's entries in descending P
+// order, 64 per batch, score the unvisited ones and keep each lane's best
+// (largest key, then smallest city).  Every deviate is below 1, so no city
+// scores above its P: once the smallest P of a batch is below the best score
+// so far, no later entry can reach it and the step is decided.  Returns the
+// city, or -1 if `walk` batches did not decide it.
+__device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cur,
+                                               const uint32_t* visited, int32_t lane, int32_t s,
+                                               int32_t ant, uint32_t& batches_read) {
+    const size_t off = static_cast<size_t>(cur) * I.ld;
+    const float* ps = I.Ps + off;
+    const uint16_t* js = I.Js + off;
+    int32_t best_key = -1;
+    int32_t best_j = 0x7FFFFFFF;
+    const int32_t batches = min(I.walk, (I.n + kWave - 1) / kWave);
+    for (int32_t k = 0; k < batches; ++k) {
+        const int32_t pos = k * kWave + lane;
+        float p = 0.0f;
+        if (pos < I.n) {
+            p = ps[pos];
+            const int32_t j = js[pos];
+            if (!((visited[j >> 5] >> (j & 31)) & 1u)) {
+                const PhiloxOut r = philox10_block(static_cast<uint32_t>(j >> 2),
+                                                   static_cast<uint32_t>(s),
+                                                   static_cast<uint32_t>(ant), I.iter, I.key0,
+                                                   I.key1);
+                const int32_t q = j & 3;
+                const uint32_t w = q == 0 ? r.w0 : (q == 1 ? r.w1 : (q == 2 ? r.w2 : r.w3));
+                const int32_t key = score_key(p, w, 0u);
+                if (key > best_key || (key == best_key && j < best_j)) {
+                    best_key = key;
+                    best_j = j;
+                }
+            }
+        }
+        ++batches_read;
+        const int32_t top = group_reduce<kWave, true>(best_key);
+        const float p_last = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p), kWave - 1));
+        if (top >= 0 && p_last < __int_as_float(top))
+            return group_reduce<kWave, false>(best_key == top ? best_j : 0x7FFFFFFF);
+    }
+    return -1;
+}
+
+template <int G, bool LIVE, int SEL = kSelAdaIR>
 __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nants,
                                 uint32_t* __restrict__ lds) {
+    static_assert(SEL != kSelSorted || (G == kWave && LIVE), "sorted walk: 64 lanes, live list");
     const int32_t lane = threadIdx.x & (kWave - 1);
     const int32_t g = lane / G;
     const int32_t gl = lane % G;
@@ -118,6 +341,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         for (int32_t i = gl; i < nblk; i += G) live[i] = static_cast<uint16_t>(i);
     }
     int32_t nlive = nblk;
+    uint32_t walk_batches = 0, scanned_steps = 0, scanned_blocks = 0;
     __builtin_amdgcn_wave_barrier();
 
     // Start city (Sec. 2.2 initialization): word 0 of counter (0, 0, ant, iter).
@@ -131,7 +355,23 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     float edge = 0.0f;  // length of the previous step's edge, added one step late
 
     for (int32_t s = 0; s < n; ++s) {
-        if (s > 0) {
+        int32_t walked = -1;
+        if constexpr (SEL == kSelSorted) {
+            if (s > 0) {
+                walked = group_uniform<G>(sorted_walk(I, cur, visited, gl, s, ant, walk_batches));
+                if (walked < 0) {
+                    ++scanned_steps;
+                    scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
+                }
+            }
+        }
+        if (SEL == kSelRoulette && s > 0) {
+            const float* row = I.P + static_cast<size_t>(cur) * I.ld;
+            next = group_uniform<G>(roulette_select<G, LIVE>(I, row, visited, live,
+                                                              LIVE ? nlive : nblk, gl, g, s, ant));
+        } else if (walked >= 0) {
+            next = walked;
+        } else if (s > 0) {
             const float* row = I.P + static_cast<size_t>(cur) * I.ld;
             int32_t best_key = -1;
             int32_t best_j = 0x7FFFFFFF;
@@ -209,15 +449,22 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         I.pred[static_cast<size_t>(start) * I.m_stride + ant] = cur;
         len += static_cast<double>(I.dist[static_cast<size_t>(cur) * I.ld + start]);
         I.lengths[ant] = static_cast<float>(len);
+        if constexpr (SEL == kSelSorted) {
+            if (I.walk_stats) {
+                atomicAdd(I.walk_stats + 0, static_cast<unsigned long long>(walk_batches));
+                atomicAdd(I.walk_stats + 1, static_cast<unsigned long long>(scanned_steps));
+                atomicAdd(I.walk_stats + 2, static_cast<unsigned long long>(scanned_blocks));
+            }
+        }
     }
 }
 
-template <int G, bool LIVE>
+template <int G, bool LIVE, int SEL>
 __global__ __launch_bounds__(kWave) void construct_kernel(InstanceView I, int32_t m) {
     extern __shared__ uint32_t lds[];
     constexpr int32_t kGroups = kWave / G;
     const int32_t ant0 = static_cast<int32_t>(blockIdx.x) * kGroups;
-    construct_group<G, LIVE>(I, ant0, min(kGroups, m - ant0), lds);
+    construct_group<G, LIVE, SEL>(I, ant0, min(kGroups, m - ant0), lds);
 }
 
 __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uint32_t ant,
@@ -230,12 +477,24 @@ __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uin
 }
 
 template <int G, bool LIVE>
-hipError_t launch_one(const InstanceView& I, int32_t m, hipStream_t stream) {
+hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipStream_t stream) {
     constexpr int32_t kGroups = kWave / G;
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(kGroups) *
                        static_cast<size_t>(group_lds_words(I.n, LIVE));
-    hipLaunchKernelGGL((construct_kernel<G, LIVE>), dim3((m + kGroups - 1) / kGroups),
-                       dim3(kWave), lds, stream, I, m);
+    const dim3 grid((m + kGroups - 1) / kGroups);
+    if (selection == kSelRoulette) {
+        hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelRoulette>), grid, dim3(kWave), lds,
+                           stream, I, m);
+    } else if (selection == kSelSorted) {
+        if constexpr (G == kWave && LIVE)
+            hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelSorted>), grid, dim3(kWave), lds,
+                               stream, I, m);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelAdaIR>), grid, dim3(kWave), lds,
+                           stream, I, m);
+    }
     return hipGetLastError();
 }
 
@@ -258,33 +517,45 @@ __device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchP
     I.key0 = inst.key0;
     I.key1 = inst.key1;
     I.iter = iter;
+    I.Ps = nullptr;
+    I.Js = nullptr;
+    I.walk = 0;
+    I.walk_stats = nullptr;
     construct_group<G, LIVE>(I, ant0, nants, lds);
 }
 
-// Each wave repeatedly takes the next task (instance, first ant, ant count,
-// schedule) from a queue ordered largest instance first, until the queue is
-// empty.  Every wave reaches the exit: the queue is finite and each task is
+// Each wave takes tasks (instance, first ant, ant count, schedule) from its
+// home queue (its workgroup index mod kQueues), then from the other queues in
+// turn, until all are empty.  Every wave reaches the exit: each queue is
+// finite, a wave leaves a queue at its first empty read, and each task is
 // bounded by its instance size.
 __global__ __launch_bounds__(kWave) void batch_construct_kernel(
-    const BatchInstance* __restrict__ insts, const BatchTask* __restrict__ tasks, int32_t ntasks,
-    uint32_t* __restrict__ queue, const IterState* __restrict__ state, BatchPools pools) {
+    const BatchInstance* __restrict__ insts, const BatchTask* __restrict__ tasks,
+    const int32_t* __restrict__ queue_start, uint32_t* __restrict__ queues,
+    const IterState* __restrict__ state, BatchPools pools) {
     extern __shared__ uint32_t lds[];
     const uint32_t iter = state->iter;
-    for (;;) {
-        uint32_t t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= static_cast<uint32_t>(ntasks)) break;
-        const BatchTask task = tasks[t];
-        const BatchInstance inst = insts[task.instance];
-        switch (task.schedule) {
-            case kSched16: run_task<16, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
-            case kSched32: run_task<32, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
-            case kSched32Live: run_task<32, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
-            case kSched64: run_task<64, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
-            default: run_task<64, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
+    const int32_t home = static_cast<int32_t>(blockIdx.x % kQueues);
+    for (int32_t k = 0; k < kQueues; ++k) {
+        const int32_t q = (home + k) % kQueues;
+        const int32_t begin = queue_start[q];
+        const uint32_t size = static_cast<uint32_t>(queue_start[q + 1] - begin);
+        for (;;) {
+            uint32_t t = 0;
+            if (threadIdx.x == 0) t = atomicAdd(queues + q, 1u);
+            t = __builtin_amdgcn_readfirstlane(t);
+            if (t >= size) break;
+            const BatchTask task = tasks[begin + static_cast<int32_t>(t)];
+            const BatchInstance inst = insts[task.instance];
+            switch (task.schedule) {
+                case kSched16: run_task<16, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+                case kSched32: run_task<32, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+                case kSched32Live: run_task<32, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
+                case kSched64: run_task<64, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+                default: run_task<64, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -316,19 +587,26 @@ size_t wave_lds_bytes(int32_t n, int32_t sched) {
            static_cast<size_t>(group_lds_words(n, schedule_live(sched)));
 }
 
+bool roulette_fits(int32_t n, int32_t sched) {
+    const int32_t G = schedule_lanes(sched);
+    const int32_t nblk = (n + 3) >> 2;
+    return (nblk + G - 1) / G <= G;
+}
+
 hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched,
-                                 hipStream_t stream) {
+                                 int32_t selection, hipStream_t stream) {
     switch (sched) {
-        case kSched16: return launch_one<16, false>(I, m, stream);
-        case kSched32: return launch_one<32, false>(I, m, stream);
-        case kSched32Live: return launch_one<32, true>(I, m, stream);
-        case kSched64: return launch_one<64, false>(I, m, stream);
-        default: return launch_one<64, true>(I, m, stream);
+        case kSched16: return launch_one<16, false>(I, m, selection, stream);
+        case kSched32: return launch_one<32, false>(I, m, selection, stream);
+        case kSched32Live: return launch_one<32, true>(I, m, selection, stream);
+        case kSched64: return launch_one<64, false>(I, m, selection, stream);
+        default: return launch_one<64, true>(I, m, selection, stream);
     }
 }
 
 hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
-                            uint64_t seed, uint32_t iter, int32_t sched, hipStream_t stream) {
+                            uint64_t seed, uint32_t iter, int32_t sched, int32_t selection,
+                            int32_t walk, hipStream_t stream) {
     InstanceView I;
     I.P = B.P;
     I.dist = B.dist;
@@ -342,13 +620,18 @@ hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, 
     I.key0 = static_cast<uint32_t>(seed);
     I.key1 = static_cast<uint32_t>(seed >> 32);
     I.iter = iter;
-    return launch_construct_view(I, m, sched, stream);
+    I.Ps = B.Ps;
+    I.Js = B.Js;
+    I.walk = walk;
+    I.walk_stats = B.walk_stats;
+    return launch_construct_view(I, m, sched, selection, stream);
 }
 
 hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
                                   int32_t grid, hipStream_t stream) {
+    (void)ntasks;
     hipLaunchKernelGGL(batch_construct_kernel, dim3(grid), dim3(kWave), lds_bytes, stream,
-                       BD.insts, BD.tasks, ntasks, BD.queue, BD.state, BD.pools);
+                       BD.insts, BD.tasks, BD.queue_start, BD.queue, BD.state, BD.pools);
     return hipGetLastError();
 }
 

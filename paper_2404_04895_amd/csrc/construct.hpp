@@ -18,7 +18,14 @@ struct InstanceView {
     int32_t* pred;       // n x m_stride
     int32_t m_stride;
     uint32_t key0, key1, iter;
+    const float* Ps;     // n x ld rows of P sorted by value (sorted walk only)
+    const uint16_t* Js;  // n x ld city of each sorted entry
+    int32_t walk;        // sorted batches per step before the scan
+    unsigned long long* walk_stats;  // sorted walk: batches read, steps scanned, blocks scanned
 };
+
+// Per-step selection rules (the ACO_SELECT_* codes of the C ABI).
+enum : int32_t { kSelAdaIR = 0, kSelRoulette = 1, kSelSorted = 2 };
 
 // Construct schedules: lanes per ant and whether the live-block list is kept.
 // The numeric codes are the ACO_SCHED_* values of the C ABI.
@@ -87,18 +94,25 @@ struct BatchPools {
     BestRecord* best;
 };
 
+// Construct task queues of the batched engine: one per XCD.  Persistent
+// wave w drains queue w mod kQueues first (workgroups are dispatched to the
+// XCDs in turn), then helps the others, so an instance's rows stay in the
+// L2 of the XCD that runs its ants.
+constexpr int32_t kQueues = 8;
+
 struct BatchDevice {
     BatchInstance* insts;
-    BatchTask* tasks;
+    BatchTask* tasks;        // queue by queue
+    int32_t* queue_start;    // kQueues + 1: first task of each queue, then the total
     RowTask* rows;
-    uint32_t* queue;
+    uint32_t* queue;         // kQueues counters
     IterState* state;
     float* gammas;  // T + 1 entries
     BatchPools pools;
 };
 
 hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched,
-                                 hipStream_t stream);
+                                 int32_t selection, hipStream_t stream);
 hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
                                   int32_t grid, hipStream_t stream);
 hipError_t launch_batch_rows(const BatchDevice& BD, int32_t nrows, int32_t max_ld,

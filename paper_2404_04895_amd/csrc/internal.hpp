@@ -36,11 +36,15 @@ struct Buffers {
     float* row_min;     // n: nearest-neighbour distance of each city
     double* lower_bound;// 1: sum of row_min
     uint32_t* flags;    // 4 validation flags
+    float* Ps;          // n x ld: each row of P sorted by value, descending
+    uint16_t* Js;       // n x ld: the city of each entry of Ps
+    unsigned long long* walk_stats;  // 3: sorted batches read, steps scanned, blocks scanned
 };
 
 struct Layout {
     size_t off_dist, off_tau, off_P, off_eta, off_tours, off_lengths, off_succ, off_pred,
-        off_weight, off_best_tour, off_best, off_row_min, off_lower_bound, off_flags, total;
+        off_weight, off_best_tour, off_best, off_row_min, off_lower_bound, off_flags, off_Ps,
+        off_Js, off_walk_stats, total;
 };
 
 Layout make_layout(int32_t n, int32_t ld, int32_t m_max);
@@ -63,8 +67,20 @@ hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, 
                            double* lower_bound, uint32_t* flags, hipStream_t stream);
 hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,
                               hipStream_t stream);
+// selection: ACO_SELECT_* (the roulette wheel needs roulette_fits; the sorted
+// walk needs the sorted rows in B.Ps / B.Js and the 64-lane live schedule).
+// walk: batches of 64 sorted entries a step reads before it falls back to
+// the scan (ACO_SELECT_ADAIR_SORTED only).
 hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
-                            uint64_t seed, uint32_t iter, int32_t sched, hipStream_t stream);
+                            uint64_t seed, uint32_t iter, int32_t sched, int32_t selection,
+                            int32_t walk, hipStream_t stream);
+// Sort every row of P by value, descending, ties by city ascending, and clear
+// the sorted walk's three counters.
+hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, float* Ps, uint16_t* Js,
+                            unsigned long long* walk_stats, hipStream_t stream);
+// Whether schedule `sched` can run the Roulette Wheel at n cities: the
+// running totals of the ceil(ceil(n/4)/G) chunks of a row live one per lane.
+bool roulette_fits(int32_t n, int32_t sched);
 hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, float Q,
                                   int32_t S, hipStream_t stream);
 hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
@@ -76,6 +92,7 @@ hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32
 hipError_t launch_uniforms(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
                            int32_t count, float* out, hipStream_t stream);
 hipError_t prepare_kernels();
+hipError_t prepare_sort_kernel();
 
 // Error reporting shared by the C ABI files (thread-local message).
 aco_status fail(aco_status st, const char* fmt, ...);

@@ -408,7 +408,7 @@ __global__ void batch_advance_kernel(IterState* __restrict__ state,
     s.t += 1;
     s.gamma_next = gammas[min(s.t + 1, s.T)];
     *state = s;
-    *queue = 0u;
+    for (int32_t q = 0; q < kQueues; ++q) queue[q] = 0u;
 }
 
 __global__ void batch_arm_kernel(IterState* __restrict__ state, const float* __restrict__ gammas,
@@ -419,7 +419,7 @@ __global__ void batch_arm_kernel(IterState* __restrict__ state, const float* __r
     s.T = T;
     s.gamma_next = gammas[min(1, T)];
     *state = s;
-    *queue = 0u;
+    for (int32_t q = 0; q < kQueues; ++q) queue[q] = 0u;
 }
 
 }  // namespace
@@ -429,9 +429,11 @@ hipError_t prepare_kernels() {
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(sizeof(double) * ACO_LDS_ROW_MAX));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(batch_rows_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               static_cast<int>(sizeof(double) * ACO_LDS_ROW_MAX));
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(batch_rows_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            static_cast<int>(sizeof(double) * ACO_LDS_ROW_MAX));
+    if (e != hipSuccess) return e;
+    return prepare_sort_kernel();
 }
 
 hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,

@@ -1,0 +1,165 @@
+"""The sorted walk (ACO_SELECT_ADAIR_SORTED) against the oracle, through the C ABI.
+
+The walk must choose exactly the city the full AdaIR argmax chooses, so the
+bar is the plain AdaIR bar: tours and FP32 lengths bit-exact against the
+oracle's construct on the same P.  The cases cover the walk's exits:
+- the walk decides the step;
+- the walk runs out of batches and the scan decides;
+- the walk is off (0 batches);
+- rows where many entries are exactly 0 or subnormal.
+They also cover pheromone that has converged over many iterations, where P is
+steep.  The sorted rows themselves are checked as sorted permutations.
+"""
+import numpy as np
+import pytest
+
+import aco_instances as inst
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _colony(D, alpha, beta, rho, m_max, **kw):
+    torch = _torch()
+    from paper_2404_04895_amd import Colony
+    return Colony(torch.from_numpy(D).cuda(), alpha, beta, rho, 1.0, m_max, **kw)
+
+
+def _check_sorted_rows(col, P):
+    Ps, Js = col.sorted_rows()
+    Ps = Ps.cpu().numpy()
+    Js = Js.cpu().numpy().view(np.uint16).astype(np.int64)
+    n = P.shape[0]
+    for c in range(n):
+        assert sorted(Js[c]) == list(range(n)), "row %d is not a permutation" % c
+        assert np.array_equal(Ps[c], P[c, Js[c]])
+        assert np.all(np.diff(Ps[c]) <= 0)
+        eq = np.diff(Ps[c]) == 0
+        assert np.all(np.diff(Js[c])[eq] > 0)  # ties by ascending city
+
+
+@pytest.mark.parametrize("n,m", [(3, 1), (5, 5), (31, 9), (64, 64), (67, 40), (257, 64),
+                                 (1000, 24), (1100, 16)])
+def test_sorted_walk_bit_exact(n, m):
+    torch = _torch()
+    D = inst.distance_matrix(inst.uniform_cities(n, 3000 + n))
+    col = _colony(D, 1.0, 2.0, 0.2, max(m, 2))
+    col.transition(1.5)
+    col.sync()
+    P = col.P().cpu().numpy()
+    seed, it = 99 + n, 5
+    o_tours, o_len = oracle.construct(P, D, seed, it, np.arange(m))
+    col.set_selection("adair-sorted")
+    steps = m * (n - 1)
+    for walk in (2, 0, 1, 8, 256):
+        col.set_sorted_walk(walk)
+        col.construct(m, seed, it)
+        col.sync()
+        assert np.array_equal(col.tours(m).cpu().numpy(), o_tours), "walk %d" % walk
+        assert np.array_equal(col.lengths(m).cpu().numpy().view(np.uint32), o_len.view(np.uint32))
+        batches, scanned, blocks = col.sorted_walk_stats()
+        nb = -(-n // 64)
+        if walk == 0:
+            assert (batches, scanned) == (0, steps)
+        else:
+            # every step reads at least one batch; a step that falls to the scan read all it may
+            assert steps <= batches <= steps * min(walk, nb)
+            assert batches >= steps + scanned * (min(walk, nb) - 1)
+        assert 0 <= scanned <= steps
+        assert scanned <= blocks <= scanned * ((n + 3) // 4)
+    if n <= 300:
+        _check_sorted_rows(col, P)
+    col.close()
+
+
+def test_sorted_walk_converged_pheromone():
+    """After 60 iterations tau has concentrated: steep rows, where the walk
+    decides early; the tours still equal the oracle's."""
+    torch = _torch()
+    n, m = 400, 64
+    D = inst.distance_matrix(inst.clustered_cities(n, 12, 8, 0.03))
+    col = _colony(D, 1.0, 3.0, 0.1, m)
+    col.run(m, 3, 60)
+    col.transition(1.2)
+    col.sync()
+    P = col.P().cpu().numpy()
+    o_tours, o_len = oracle.construct(P, D, 7, 61, np.arange(m))
+    col.set_selection("adair-sorted")
+    col.construct(m, 7, 61)
+    col.sync()
+    assert np.array_equal(col.tours(m).cpu().numpy(), o_tours)
+    assert np.array_equal(col.lengths(m).cpu().numpy().view(np.uint32), o_len.view(np.uint32))
+    _check_sorted_rows(col, P)
+    col.close()
+
+
+def test_sorted_walk_zero_and_subnormal_rows():
+    torch = _torch()
+    n, m = 300, 48
+    D = inst.distance_matrix(inst.clustered_cities(n, 9, 4, 0.02))
+    col = _colony(D, 1.0, 40.0, 0.2, m)
+    col.transition(1.0)
+    col.sync()
+    P = col.P().cpu().numpy()
+    off = ~np.eye(n, dtype=bool)
+    assert np.sum(P[off] == 0) > 0.5 * off.sum()
+    o_tours, o_len = oracle.construct(P, D, 5, 1, np.arange(m))
+    col.set_selection("adair-sorted")
+    for walk in (2, 64):
+        col.set_sorted_walk(walk)
+        col.construct(m, 5, 1)
+        col.sync()
+        assert np.array_equal(col.tours(m).cpu().numpy(), o_tours)
+    col.close()
+
+
+def test_sorted_walk_free_run_and_rejections():
+    torch = _torch()
+    from paper_2404_04895_amd import AcoError
+    n, m, T = 40, 40, 30
+    D = inst.distance_matrix(inst.uniform_cities(n, 8))
+    col = _colony(D, 1.0, 2.0, 0.3, m)
+    col.set_selection("adair-sorted")
+    tour, L = col.run(m, 4, T)
+    ref = oracle.run(D, m, 1.0, 2.0, 0.3, 1.0, 4, T)
+    assert L == ref["best_len"]
+    assert np.array_equal(col.tau().cpu().numpy(), ref["tau"])
+    with pytest.raises(AcoError):
+        col.set_sorted_walk(-1)
+    with pytest.raises(AcoError):
+        col.set_sorted_walk(257)
+    col.set_schedule(1)  # 32 lanes: the walk needs 64
+    col.transition(1.0)
+    with pytest.raises(AcoError):
+        col.construct(m, 1, 0)
+    col.close()
+
+
+def test_sorted_walk_full_size_clustered_n5000():
+    """The benchmark workload and launch shape; sampled ants against the oracle."""
+    torch = _torch()
+    w = inst.WORKLOADS["clustered-n5000-m5000"]
+    D = w.dist(0)
+    n, m = w.n, w.m
+    col = _colony(D, w.alpha, w.beta, w.rho, m)
+    col.set_selection("adair-sorted")
+    col.transition(1.5)
+    col.construct(m, 1, 0)
+    col.sync()
+    P = col.P().cpu().numpy()
+    tours = col.tours(m).cpu().numpy()
+    lengths = col.lengths(m).cpu().numpy()
+    srt = np.sort(tours, axis=1)
+    assert np.array_equal(srt, np.broadcast_to(np.arange(n, dtype=np.int32), srt.shape))
+    sample = np.array([0, 1, 2499, 4998, 4999])
+    o_tours, o_len = oracle.construct(P, D, 1, 0, sample)
+    assert np.array_equal(tours[sample], o_tours)
+    assert np.array_equal(lengths[sample].view(np.uint32), o_len.view(np.uint32))
+    col.close()
