@@ -5,10 +5,18 @@ construction for every ant (with tour lengths and successor/predecessor
 maps), best-so-far, elite weights, index-mapped deposit, evaporation and the
 next transition matrix.  Inputs are resident in HBM before timing starts.
 
+The construct runs the sorted walk by default (--selection adair-sorted).  It
+picks exactly the AdaIR argmax, bit for bit, without scoring the cities that
+provably cannot win.  Its rows are sorted in the update that builds P.
+--selection adair runs the full scan that scores every unvisited city.
+
 Prints one JSON line.  value = ant-steps per second over the whole iteration
-(m * (n-1) per step); roofline = the construct kernel's algorithmic HBM bytes
-per launch over its measured average duration; cpu_baseline = the CPU oracle
-on a bounded sample of the same workload.
+(m * (n-1) per step).  roofline = the construct kernel's algorithmic HBM bytes
+per launch over its measured average duration.  For the sorted walk these
+bytes are what the kernel reports it read: 384 B per batch of 64 sorted
+entries, 16 B per block of a fallback scan, 8 B per step.  roofline_full_scan
+= the same for the full scan, timed on the same colony right after.
+cpu_baseline = the CPU oracle on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -21,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "construct_counters.json")
+COUNTERS_FILES = {"adair": os.path.join(ROOT, "profiles", "construct_counters.json"),
+                  "adair-sorted": os.path.join(ROOT, "profiles", "construct_sorted_counters.json")}
 KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/philox.hpp"]
 
 
@@ -39,11 +48,23 @@ def construct_bytes(n, m):
     return m * (n - 1) * (4 * n + 8)
 
 
-def counter_traffic(n, m):
+def sorted_walk_bytes(stats, launches, n, m):
+    """Algorithmic bytes of one sorted-walk construct launch from the kernel's
+    own counts: each batch is 64 entries of FP32 value + uint16 city, each
+    fallback block one float4 row slice, and every step writes its tour entry
+    and gathers its distance."""
+    batches, _, blocks = stats
+    return (batches * 64 * 6 + blocks * 16) / launches + m * (n - 1) * 8
+
+
+def counter_traffic(n, m, selection="adair"):
     """HBM traffic per construct launch from committed rocprofv3 counters, or
     None if they were taken on another workload or an older kernel."""
+    path = COUNTERS_FILES.get(selection)
+    if path is None:
+        return None
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
@@ -223,8 +244,13 @@ def main():
     ap.add_argument("--workload", default="clustered-n5000-m5000")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--selection", default="adair", choices=["adair", "adair-sorted", "roulette"],
+    ap.add_argument("--selection", default="adair-sorted",
+                    choices=["adair", "adair-sorted", "roulette"],
                     help="per-step selection rule of the construct")
+    ap.add_argument("--no-full-scan-reference", action="store_true",
+                    help="skip the full-scan reference timing after the sorted walk")
+    ap.add_argument("--schedule", type=int, default=None,
+                    help="construct schedule code (ACO_SCHED_*); default: by size")
     ap.add_argument("--walk", type=int, default=None,
                     help="sorted batches per step before the scan (adair-sorted)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -258,6 +284,8 @@ def main():
     col.set_selection(args.selection)
     if args.walk is not None:
         col.set_sorted_walk(args.walk)
+    if args.schedule is not None:
+        col.set_schedule(args.schedule)
     stream = torch.cuda.current_stream()
 
     def step(t, ev=None):
@@ -280,6 +308,9 @@ def main():
     torch.cuda.synchronize()
     P_host = col.P().cpu().numpy() if not args.no_cpu_baseline else None
 
+    sorted_walk = args.selection == "adair-sorted"
+    if sorted_walk:
+        col.sorted_walk_stats()  # reset the counts
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -294,10 +325,38 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     ant_steps = m * (n - 1)
     value = ant_steps * args.steps / elapsed
-    bytes_launch = construct_bytes(n, m)
+    walk = None
+    if sorted_walk:
+        stats = col.sorted_walk_stats()
+        bytes_launch = sorted_walk_bytes(stats, args.steps, n, m)
+        walk = {"batches_per_step": stats[0] / (args.steps * ant_steps),
+                "scanned_step_fraction": stats[1] / (args.steps * ant_steps),
+                "blocks_per_scanned_step": stats[2] / max(stats[1], 1)}
+    else:
+        bytes_launch = construct_bytes(n, m)
     achieved = bytes_launch / avg_construct_s / 1e9
-    traffic = counter_traffic(n, m)
+    traffic = counter_traffic(n, m, args.selection)
     _, best_len, best_iter = col.best()
+
+    reference = None
+    if sorted_walk and not args.no_full_scan_reference:
+        # the full scan on the same colony, continuing the same run, on the
+        # schedule the library picks for it
+        col.set_selection("adair")
+        col.set_schedule(-1)
+        k2 = min(args.steps, 5)
+        ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(k2)]
+        for k in range(k2):
+            step(args.warmup + args.steps + k, ev2[k])
+        torch.cuda.synchronize()
+        ref_s = sum(a.elapsed_time(b) for a, b in ev2) / k2 / 1e3
+        ref_bytes = construct_bytes(n, m)
+        reference = {"bound": "hbm", "kernel": "construct_kernel (full scan)",
+                     "achieved": ref_bytes / ref_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ref_bytes / ref_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(n, m, "adair"), "bytes_per_launch": ref_bytes,
+                     "avg_launch_ms": ref_s * 1e3, "launches": k2}
 
     line = {
         "metric": "ant-steps/sec & % HBM peak; learned-vs-plain best-tour gap at equal time",
@@ -317,13 +376,18 @@ def main():
                        w.family, w.clusters, w.sigma) if w.family != "uniform" else "uniform",
                    "gamma": [w.gamma_max, w.gamma_min], "seed": args.seed,
                    "selection": args.selection},
-        "roofline": {"bound": "hbm", "kernel": "construct_kernel", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": avg_construct_s * 1e3},
+        "roofline": {"bound": "hbm",
+                     "kernel": "construct_kernel (sorted walk)" if sorted_walk else "construct_kernel",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_construct_s * 1e3},
         "construct_ant_steps_per_s": ant_steps / avg_construct_s,
         "best_len": best_len,
     }
+    if walk is not None:
+        line["sorted_walk"] = walk
+    if reference is not None:
+        line["roofline_full_scan"] = reference
     col.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, D, P_host)

@@ -166,16 +166,18 @@ const float* aco_pheromone(const aco_ctx* ctx);
 const float* aco_transition_matrix(const aco_ctx* ctx);
 const int32_t* aco_tours(const aco_ctx* ctx);
 const float* aco_lengths(const aco_ctx* ctx);
-/* The rows of P sorted by the last construct under ACO_SELECT_ADAIR_SORTED,
- * n x ld: values (FP32, descending within a row) and their cities (uint16);
- * the first n entries of each row are meaningful. */
+/* The rows of P as last sorted for ACO_SELECT_ADAIR_SORTED, n x ld: values
+ * (FP32, descending within a row, ties by ascending city) and their cities
+ * (uint16).  Only the first K entries of each row are kept: K = 64 * walk
+ * rounded up to a power of two, at most n (the walk never reads further). */
 const float* aco_sorted_rows(const aco_ctx* ctx);
 const uint16_t* aco_sorted_cities(const aco_ctx* ctx);
 
-/* What the last ACO_SELECT_ADAIR_SORTED construct read (blocks): out3[0] the
- * batches of 64 sorted entries read, summed over ants and steps; out3[1] the
- * steps the walk left to the scan; out3[2] the live 4-city blocks those scans
- * read.  Errors: ACO_EINVAL for a NULL pointer. */
+/* What the ACO_SELECT_ADAIR_SORTED constructs since the previous call (or
+ * since aco_create) read, then resets the counts (blocks): out3[0] the batches
+ * of 64 sorted entries read, summed over ants and steps; out3[1] the steps the
+ * walk left to the scan; out3[2] the 4-city blocks those scans read.
+ * Errors: ACO_EINVAL for a NULL pointer. */
 aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3);
 
 /* Exponent S of the deposit quantisation: the largest S with
@@ -240,19 +242,21 @@ aco_status aco_set_selection(aco_ctx* ctx, int32_t selection);
 
 /* ACO_SELECT_ADAIR_SORTED: the same selection as ACO_SELECT_ADAIR, bit for bit,
  * found with less work.  Every deviate of Sec. 2.4 is below 1, so a city's
- * score fl32(P[c,j] * r_j) never exceeds P[c,j].  aco_construct first sorts
- * every row of P (value descending, city ascending; into workspace buffers).
+ * score fl32(P[c,j] * r_j) never exceeds P[c,j].  While this selection is set,
+ * aco_transition and aco_update also sort every row of the P they build (value
+ * descending, city ascending; into workspace buffers), and aco_construct sorts
+ * first if P has not been sorted yet.
  * A step then reads the row's entries in that order, 64 at a time, scoring
  * the unvisited ones.  It stops as soon as the smallest P of a batch is below
  * the best score found: no later city can reach that score.  If `batches`
- * batches (aco_set_sorted_walk) have not decided the step, it scans the live
- * blocks as ACO_SELECT_ADAIR does.  Runs on ACO_SCHED_G64_LIVE (chosen by
- * ACO_SCHED_AUTO; another forced schedule makes aco_construct return
- * ACO_EINVAL). */
+ * batches (aco_set_sorted_walk) have not decided the step, it scans the row's
+ * blocks (only the live ones under ACO_SCHED_G64_LIVE) as ACO_SELECT_ADAIR does.  Runs on a 64-lane schedule: ACO_SCHED_G64
+ * (chosen by ACO_SCHED_AUTO) or ACO_SCHED_G64_LIVE; another forced schedule
+ * makes aco_construct return ACO_EINVAL. */
 #define ACO_SORTED_WALK_MAX 256
 
 /* Batches of 64 sorted entries a step of ACO_SELECT_ADAIR_SORTED reads before
- * it falls back to the scan (default 2; 0 always scans).
+ * it falls back to the scan (default 8; 0 always scans).
  * Errors: ACO_EINVAL outside [0, ACO_SORTED_WALK_MAX]. */
 aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches);
 

@@ -29,7 +29,8 @@ struct aco_ctx {
     uint32_t iter = 0;         // running iteration counter used by aco_run
     int32_t schedule = -1;     // construct schedule (ACO_SCHED_*), -1: by size
     int32_t selection = ACO_SELECT_ADAIR;  // per-step selection rule (ACO_SELECT_*)
-    int32_t walk = 2;          // sorted batches a step reads before the scan
+    int32_t walk = 8;          // sorted batches a step reads before the scan
+    bool rows_sorted = false;  // Ps / Js hold the sorted rows of the current P
 };
 
 namespace {
@@ -50,6 +51,17 @@ aco_status bind_device(const aco_ctx* ctx) {
     int cur = -1;
     ACO_HIP(hipGetDevice(&cur), "hipGetDevice");
     if (cur != ctx->device) ACO_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return ACO_OK;
+}
+
+// Sort the rows of the current P for the sorted walk, unless that is done.
+aco_status sort_rows_if_needed(aco_ctx* ctx) {
+    if (ctx->selection != ACO_SELECT_ADAIR_SORTED || ctx->rows_sorted) return ACO_OK;
+    if (ctx->walk > 0)
+        ACO_HIP(aco::launch_sort_rows(ctx->buf.P, ctx->n, ctx->ld, ctx->walk, ctx->buf.Ps,
+                                      ctx->buf.Js, ctx->stream),
+                "sort rows");
+    ctx->rows_sorted = true;
     return ACO_OK;
 }
 
@@ -225,6 +237,7 @@ aco_status aco_create(const float* dist_dev, int32_t n, float alpha, float beta,
     if (e == hipSuccess)
         e = hipMemcpyAsync(&lower, ctx->buf.lower_bound, sizeof(lower), hipMemcpyDeviceToHost,
                            ctx->stream);
+    if (e == hipSuccess) e = aco::launch_clear_counters(ctx->buf.walk_stats, 3, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "validate dist (read back)"));
     if (flags) {
@@ -263,6 +276,7 @@ aco_status aco_set_params(aco_ctx* ctx, const aco_params* p) {
             "reset tau");
     ACO_HIP(aco::launch_clear_best(ctx->buf.best, 1, ctx->stream), "clear best");
     ctx->have_P = false;
+    ctx->rows_sorted = false;
     ctx->have_tours = false;
     return ACO_OK;
 }
@@ -271,6 +285,7 @@ aco_status aco_set_eta(aco_ctx* ctx, const float* eta_dev) {
     if (aco_status st = check_ctx(ctx)) return st;
     if (aco_status st = bind_device(ctx)) return st;
     ctx->have_P = false;
+    ctx->rows_sorted = false;
     if (!eta_dev) {
         ctx->eta_active = false;
         return ACO_OK;
@@ -317,6 +332,7 @@ aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches) {
     if (batches < 0 || batches > ACO_SORTED_WALK_MAX)
         return fail(ACO_EINVAL, "aco_set_sorted_walk: %d outside [0, %d]", batches,
                     ACO_SORTED_WALK_MAX);
+    if (batches > ctx->walk) ctx->rows_sorted = false;  // a longer sorted prefix is needed
     ctx->walk = batches;
     return ACO_OK;
 }
@@ -329,7 +345,8 @@ aco_status aco_transition(aco_ctx* ctx, float gamma) {
                              ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma, ctx->stream),
             "transition");
     ctx->have_P = true;
-    return ACO_OK;
+    ctx->rows_sorted = false;
+    return sort_rows_if_needed(ctx);
 }
 
 aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) {
@@ -341,19 +358,17 @@ aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) 
     const bool sorted = ctx->selection == ACO_SELECT_ADAIR_SORTED;
     int32_t sched = ctx->schedule >= 0 ? ctx->schedule : aco::default_schedule(ctx->n);
     if (sorted) {
-        if (ctx->schedule >= 0 && ctx->schedule != ACO_SCHED_G64_LIVE)
-            return fail(ACO_EINVAL,
-                        "aco_construct: the sorted walk runs on ACO_SCHED_G64_LIVE only");
-        sched = ACO_SCHED_G64_LIVE;
+        if (ctx->schedule < 0) {
+            sched = ACO_SCHED_G64;
+        } else if (ctx->schedule != ACO_SCHED_G64 && ctx->schedule != ACO_SCHED_G64_LIVE) {
+            return fail(ACO_EINVAL, "aco_construct: the sorted walk needs a 64-lane schedule");
+        }
     }
     if (ctx->selection == ACO_SELECT_ROULETTE && !aco::roulette_fits(ctx->n, sched))
         return fail(ACO_EINVAL,
                     "aco_construct: schedule %d cannot run the roulette wheel at n = %d", sched,
                     ctx->n);
-    if (sorted)
-        ACO_HIP(aco::launch_sort_rows(ctx->buf.P, ctx->n, ctx->ld, ctx->buf.Ps, ctx->buf.Js,
-                                      ctx->buf.walk_stats, ctx->stream),
-                "sort rows");
+    if (aco_status st = sort_rows_if_needed(ctx)) return st;
     ACO_HIP(aco::launch_construct(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, seed, iter, sched,
                                   ctx->selection, ctx->walk, ctx->stream),
             "construct");
@@ -378,7 +393,8 @@ aco_status aco_update(aco_ctx* ctx, float gamma_next) {
             "update rows");
     ctx->have_tours = false;
     ctx->have_P = true;
-    return ACO_OK;
+    ctx->rows_sorted = false;
+    return sort_rows_if_needed(ctx);
 }
 
 aco_status aco_run(aco_ctx* ctx, int32_t m, uint64_t seed, int32_t iters,
@@ -411,6 +427,7 @@ aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3) {
             "walk stats");
     ACO_HIP(hipStreamSynchronize(ctx->stream), "walk stats (sync)");
     for (int k = 0; k < 3; ++k) out3[k] = static_cast<uint64_t>(v[k]);
+    ACO_HIP(aco::launch_clear_counters(ctx->buf.walk_stats, 3, ctx->stream), "walk stats reset");
     return ACO_OK;
 }
 
@@ -458,6 +475,7 @@ aco_status aco_set_state(aco_ctx* ctx, const float* tau_dev, uint32_t iter) {
                 "copy tau in");
     ctx->iter = iter;
     ctx->have_P = false;
+    ctx->rows_sorted = false;
     ctx->have_tours = false;
     return ACO_OK;
 }

@@ -24,7 +24,9 @@
 // tour order, rounded once to FP32 -- the fitness f of Eq. (3)), and the
 // successor / predecessor of every city, stored city-major so that the
 // update kernel reads one contiguous row of each per city (Eq. (2)'s index
-// matrix, held as two maps).
+// matrix, held as two maps).  They are written once per G steps from a
+// register window, so no scattered store or distance gather sits between
+// one step's decision and the next step's loads.
 #include "construct.hpp"
 
 namespace aco {
@@ -94,6 +96,51 @@ template <int G>
 __device__ __forceinline__ int32_t group_uniform(int32_t v) {
     if constexpr (G == 64) return __builtin_amdgcn_readfirstlane(v);
     return v;
+}
+
+// ---- per-window output -----------------------------------------------------
+
+// Lane k of the calling lane's group (k the same on every lane of the wave).
+template <int G>
+__device__ __forceinline__ int32_t group_lane(int32_t v, int32_t k) {
+    if constexpr (G == kWave) {
+        return __builtin_amdgcn_readlane(v, k);
+    } else {
+        const int32_t g = (threadIdx.x & (kWave - 1)) / G;
+        int32_t r = 0;
+#pragma unroll
+        for (int32_t q = 0; q < kWave / G; ++q) {
+            const int32_t t = __builtin_amdgcn_readlane(v, q * G + k);
+            if (g == q) r = t;
+        }
+        return r;
+    }
+}
+
+// Write out a window of the tour: lane l of the group holds entry base + l
+// (l < cnt); `prev` is the entry before the window (-1 for the first).  Each
+// lane writes its entry and the successor / predecessor maps of the edge
+// that ends at it, and gathers that edge's length; the lengths are then
+// added to `len` one by one in tour order, so the FP64 sum is the
+// sequential one.  Runs once per G steps, which keeps scattered stores and
+// the random distance gathers out of the per-step chain.
+template <int G>
+__device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tour, int32_t ant,
+                                             int32_t base, int32_t cnt, int32_t win,
+                                             int32_t prev, int32_t gl, double& len) {
+    int32_t from = __shfl_up(win, 1, G);
+    if (gl == 0) from = prev;
+    float d = 0.0f;
+    if (gl < cnt) {
+        tour[base + gl] = win;
+        if (from >= 0) {
+            I.succ[static_cast<size_t>(from) * I.m_stride + ant] = win;
+            I.pred[static_cast<size_t>(win) * I.m_stride + ant] = from;
+            d = I.dist[static_cast<size_t>(from) * I.ld + win];
+        }
+    }
+    for (int32_t k = (prev < 0) ? 1 : 0; k < cnt; ++k)
+        len += static_cast<double>(__int_as_float(group_lane<G>(__float_as_int(d), k)));
 }
 
 // ---- roulette wheel helpers ----------------------------------------------
@@ -319,7 +366,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
 template <int G, bool LIVE, int SEL = kSelAdaIR>
 __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nants,
                                 uint32_t* __restrict__ lds) {
-    static_assert(SEL != kSelSorted || (G == kWave && LIVE), "sorted walk: 64 lanes, live list");
+    static_assert(SEL != kSelSorted || G == kWave, "the sorted walk runs with 64 lanes per ant");
     const int32_t lane = threadIdx.x & (kWave - 1);
     const int32_t g = lane / G;
     const int32_t gl = lane % G;
@@ -352,7 +399,8 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     int32_t cur = start;
     int32_t next = start;
     double len = 0.0;
-    float edge = 0.0f;  // length of the previous step's edge, added one step late
+    int32_t win = 0;     // lane (s mod G) keeps tour entry s until its window is written
+    int32_t prev = -1;   // last entry of the previous window
 
     for (int32_t s = 0; s < n; ++s) {
         int32_t walked = -1;
@@ -408,20 +456,18 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
             const int32_t top = group_reduce<G, true>(best_key);
             next = group_uniform<G>(group_reduce<G, false>(best_key == top ? best_j : 0x7FFFFFFF));
         }
-        // record the step: visited bit, tour entry, successor/predecessor maps
+        // record the step: visited bit now; tour entry, maps and length per window
         const int32_t word = next >> 5;
         const uint32_t bits = visited[word] | (1u << (next & 31));
         __builtin_amdgcn_wave_barrier();
-        if (gl == 0) {
-            visited[word] = bits;
-            tour[s] = next;
-            if (s > 0) {
-                I.succ[static_cast<size_t>(cur) * I.m_stride + ant] = next;
-                I.pred[static_cast<size_t>(next) * I.m_stride + ant] = cur;
-            }
+        if (gl == 0) visited[word] = bits;
+        if (gl == (s & (G - 1))) win = next;
+        if ((s & (G - 1)) == G - 1 || s == n - 1) {
+            const int32_t base = s & ~(G - 1);
+            const int32_t cnt = s - base + 1;
+            flush_window<G>(I, tour, ant, base, cnt, win, prev, gl, len);
+            prev = group_lane<G>(win, cnt - 1);
         }
-        len += static_cast<double>(edge);
-        if (s > 0) edge = I.dist[static_cast<size_t>(cur) * I.ld + next];
         cur = next;
         if constexpr (LIVE) {
             // drop the block from the live list once its last city is taken
@@ -443,7 +489,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         }
         __builtin_amdgcn_wave_barrier();
     }
-    len += static_cast<double>(edge);
+    // the closing edge, added last
     if (gl == 0) {
         I.succ[static_cast<size_t>(cur) * I.m_stride + ant] = start;
         I.pred[static_cast<size_t>(start) * I.m_stride + ant] = cur;
@@ -486,7 +532,7 @@ hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipSt
         hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelRoulette>), grid, dim3(kWave), lds,
                            stream, I, m);
     } else if (selection == kSelSorted) {
-        if constexpr (G == kWave && LIVE)
+        if constexpr (G == kWave)
             hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelSorted>), grid, dim3(kWave), lds,
                                stream, I, m);
         else

@@ -68,16 +68,19 @@ hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, 
 hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,
                               hipStream_t stream);
 // selection: ACO_SELECT_* (the roulette wheel needs roulette_fits; the sorted
-// walk needs the sorted rows in B.Ps / B.Js and the 64-lane live schedule).
+// walk needs the sorted rows in B.Ps / B.Js and a 64-lane schedule).
 // walk: batches of 64 sorted entries a step reads before it falls back to
 // the scan (ACO_SELECT_ADAIR_SORTED only).
 hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
                             uint64_t seed, uint32_t iter, int32_t sched, int32_t selection,
                             int32_t walk, hipStream_t stream);
-// Sort every row of P by value, descending, ties by city ascending, and clear
-// the sorted walk's three counters.
-hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, float* Ps, uint16_t* Js,
-                            unsigned long long* walk_stats, hipStream_t stream);
+// Sort every row of P by value, descending, ties by city ascending: the
+// first sorted_prefix(n, walk) entries of each row (all n when that is n).
+hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, int32_t walk, float* Ps,
+                            uint16_t* Js, hipStream_t stream);
+int32_t sorted_prefix(int32_t n, int32_t walk);
+// Zero `count` (<= 64) 64-bit counters with a kernel (safe under graph capture).
+hipError_t launch_clear_counters(unsigned long long* c, int32_t count, hipStream_t stream);
 // Whether schedule `sched` can run the Roulette Wheel at n cities: the
 // running totals of the ceil(ceil(n/4)/G) chunks of a row live one per lane.
 bool roulette_fits(int32_t n, int32_t sched);

@@ -2,13 +2,15 @@
 // AdaIR selection (Sec. 2.4): a step reads a row from its largest entries
 // down and stops once no later entry can win.
 //
-// One workgroup per row.  The row's n entries, with their city indices, are
-// loaded into LDS as (P bits, city) pairs; P >= +0, so the FP32 bit patterns
-// order like the values.  A bitonic network over the next power of two puts
-// them in descending order of P, ties by ascending city.  Empty slots sort
-// last.  The network is data-oblivious, so the order is the same on every
-// run.  Each compare-exchange step reads and writes LDS only, with one
-// barrier between steps.
+// One workgroup per row.  The walk reads at most `walk` batches of 64, so a
+// row needs only its first K = 64 * walk entries (rounded up to a power of
+// two) in order; when K < n a radix select finds them first.  The entries,
+// with their city indices, sit in LDS as (P bits, city) pairs; P >= +0, so
+// the FP32 bit patterns order like the values.  A bitonic network over a
+// power of two puts them in descending order of P, ties by ascending city;
+// empty slots sort last.  The network is data-oblivious, so the order is the
+// same on every run.  Each compare-exchange step reads and writes LDS only,
+// with one barrier between steps.
 #include "internal.hpp"
 
 namespace aco {
@@ -22,28 +24,17 @@ __device__ __forceinline__ bool before(uint32_t ka, uint32_t ja, uint32_t kb, ui
     return ka > kb || (ka == kb && ja < jb);
 }
 
-__global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
-    const float* __restrict__ P, int32_t n, int32_t ld, int32_t n2, float* __restrict__ Ps,
-    uint16_t* __restrict__ Js, unsigned long long* __restrict__ walk_stats) {
-    extern __shared__ uint32_t sh[];
-    uint32_t* key = sh;                                         // n2 words
-    uint16_t* city = reinterpret_cast<uint16_t*>(sh + n2);      // n2 halves
-    const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
+// Bitonic network over the n2 (a power of two) LDS slots, descending by
+// (key, then ascending city).
+__device__ __forceinline__ void bitonic_lds(uint32_t* key, uint16_t* city, int32_t n2) {
     const int32_t tid = threadIdx.x;
     const int32_t nt = blockDim.x;
-    if (blockIdx.x == 0 && tid < 3) walk_stats[tid] = 0ull;
-    for (int32_t i = tid; i < n2; i += nt) {
-        key[i] = i < n ? __float_as_uint(P[row + i]) : 0u;
-        city[i] = static_cast<uint16_t>(i < n ? i : 0xFFFF);
-    }
-    __syncthreads();
     const int32_t pairs = n2 >> 1;
     for (int32_t size = 2; size <= n2; size <<= 1) {
         for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
             for (int32_t t = tid; t < pairs; t += nt) {
                 const int32_t lo = 2 * t - (t & (stride - 1));
                 const int32_t hi = lo + stride;
-                // the final merge (size = n2) is descending everywhere
                 const bool down = (lo & size) == 0;
                 const uint32_t ka = key[lo], kb = key[hi];
                 const uint32_t ja = city[lo], jb = city[hi];
@@ -58,30 +49,169 @@ __global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
             __syncthreads();
         }
     }
+}
+
+__global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
+    const float* __restrict__ P, int32_t n, int32_t ld, int32_t n2, float* __restrict__ Ps,
+    uint16_t* __restrict__ Js) {
+    extern __shared__ uint32_t sh[];
+    uint32_t* key = sh;                                         // n2 words
+    uint16_t* city = reinterpret_cast<uint16_t*>(sh + n2);      // n2 halves
+    const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
+    const int32_t tid = threadIdx.x;
+    const int32_t nt = blockDim.x;
+    for (int32_t i = tid; i < n2; i += nt) {
+        key[i] = i < n ? __float_as_uint(P[row + i]) : 0u;
+        city[i] = static_cast<uint16_t>(i < n ? i : 0xFFFF);
+    }
+    __syncthreads();
+    bitonic_lds(key, city, n2);
     for (int32_t i = tid; i < n; i += nt) {
         Ps[row + i] = __uint_as_float(key[i]);
         Js[row + i] = city[i];
     }
 }
 
+constexpr int32_t kTopThreads = 256;
+
+// The first K entries of the full sort of a row, for K < n (K a power of two):
+// every entry whose key exceeds the K-th largest key T, and the entries equal
+// to T with the smallest cities, then sorted.  T is found by a radix select,
+// most significant byte first: four 256-bin LDS histograms over the entries
+// that match the bytes chosen so far.  The entries equal to T are ranked in
+// city order through per-thread contiguous segments and a prefix sum.
+__global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __restrict__ P,
+                                                                int32_t n, int32_t ld,
+                                                                int32_t K,
+                                                                float* __restrict__ Ps,
+                                                                uint16_t* __restrict__ Js) {
+    extern __shared__ uint32_t sh[];
+    uint32_t* hist = sh;                                          // 256
+    uint32_t* seg_count = sh + 256;                               // kTopThreads
+    uint32_t* misc = sh + 256 + kTopThreads;                      // 4
+    uint32_t* key = sh + 256 + kTopThreads + 4;                   // K
+    uint16_t* city = reinterpret_cast<uint16_t*>(key + K);        // K
+    const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(P + row);
+    const int32_t tid = threadIdx.x;
+
+    uint32_t prefix = 0u, mask = 0u;
+    uint32_t need = static_cast<uint32_t>(K);
+    for (int32_t shift = 24; shift >= 0; shift -= 8) {
+        for (int32_t i = tid; i < 256; i += kTopThreads) hist[i] = 0u;
+        __syncthreads();
+        for (int32_t i = tid; i < n; i += kTopThreads) {
+            const uint32_t k = bits[i];
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 0xFFu], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // the digit d holding the need-th largest: count from the top bin down
+            uint32_t above = 0u;
+            int32_t d = 255;
+            for (; d > 0; --d) {
+                if (above + hist[d] >= need) break;
+                above += hist[d];
+            }
+            misc[0] = static_cast<uint32_t>(d);
+            misc[1] = above;
+        }
+        __syncthreads();
+        prefix |= misc[0] << shift;
+        mask |= 0xFFu << shift;
+        need -= misc[1];
+        __syncthreads();
+    }
+    const uint32_t T = prefix;  // `need` (>= 1) entries equal to T complete the top K
+
+    // rank the entries equal to T in city order: contiguous segments per thread
+    const int32_t seg = (n + kTopThreads - 1) / kTopThreads;
+    const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
+    uint32_t eq = 0u;
+    for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
+    seg_count[tid] = eq;
+    if (tid == 0) misc[2] = 0u;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0u;
+        for (int32_t t = 0; t < kTopThreads; ++t) {
+            const uint32_t c = seg_count[t];
+            seg_count[t] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    // entries above T take slots need .. K-1 (their order is fixed by the sort
+    // below); the equal ones of rank < need take slots 0 .. need-1
+    uint32_t rank = seg_count[tid];
+    for (int32_t i = lo; i < hi; ++i) {
+        const uint32_t k = bits[i];
+        int32_t slot = -1;
+        if (k > T) {
+            slot = static_cast<int32_t>(need + atomicAdd(&misc[2], 1u));
+        } else if (k == T) {
+            if (rank < need) slot = static_cast<int32_t>(rank);
+            ++rank;
+        }
+        if (slot >= 0 && slot < K) {
+            key[slot] = k;
+            city[slot] = static_cast<uint16_t>(i);
+        }
+    }
+    __syncthreads();
+    bitonic_lds(key, city, K);
+    for (int32_t i = tid; i < K; i += kTopThreads) {
+        Ps[row + i] = __uint_as_float(key[i]);
+        Js[row + i] = city[i];
+    }
+}
+
+__global__ void clear_counters_kernel(unsigned long long* __restrict__ c, int32_t count) {
+    const int32_t i = threadIdx.x;
+    if (i < count) c[i] = 0ull;
+}
+
 }  // namespace
 
-hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, float* Ps, uint16_t* Js,
-                            unsigned long long* walk_stats, hipStream_t stream) {
+hipError_t launch_clear_counters(unsigned long long* c, int32_t count, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, stream, c, count);
+    return hipGetLastError();
+}
+
+int32_t sorted_prefix(int32_t n, int32_t walk) {
+    int32_t k = 64;
+    while (k < 64 * walk) k <<= 1;
+    return k < n ? k : n;
+}
+
+hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, int32_t walk, float* Ps,
+                            uint16_t* Js, hipStream_t stream) {
+    const int32_t K = sorted_prefix(n, walk);
+    if (K < n) {
+        const size_t lds = sizeof(uint32_t) * (256 + kTopThreads + 4) +
+                           static_cast<size_t>(K) * (sizeof(uint32_t) + sizeof(uint16_t));
+        hipLaunchKernelGGL(topk_rows_kernel, dim3(n), dim3(kTopThreads), lds, stream, P, n, ld,
+                           K, Ps, Js);
+        return hipGetLastError();
+    }
     int32_t n2 = 2;
     while (n2 < n) n2 <<= 1;
     const int32_t threads = min(kSortThreads, max(64, n2 >> 1));
     const size_t lds = static_cast<size_t>(n2) * (sizeof(uint32_t) + sizeof(uint16_t));
     hipLaunchKernelGGL(sort_rows_kernel, dim3(n), dim3(threads), lds, stream, P, n, ld, n2, Ps,
-                       Js, walk_stats);
+                       Js);
     return hipGetLastError();
 }
 
 hipError_t prepare_sort_kernel() {
-    // n2 <= 16384: 96 KB of LDS
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(sort_rows_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               static_cast<int>(16384 * (sizeof(uint32_t) + sizeof(uint16_t))));
+    // n2 <= 16384: 96 KB of LDS; the top-K kernel needs K < n <= 16384 slots
+    const int bytes = static_cast<int>(16384 * (sizeof(uint32_t) + sizeof(uint16_t)) +
+                                       sizeof(uint32_t) * (256 + kTopThreads + 4));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sort_rows_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(topk_rows_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace aco
