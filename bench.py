@@ -13,8 +13,8 @@ provably cannot win.  Its rows are sorted in the update that builds P.
 Prints one JSON line.  value = ant-steps per second over the whole iteration
 (m * (n-1) per step).  roofline = the construct kernel's algorithmic HBM bytes
 per launch over its measured average duration.  For the sorted walk these
-bytes are what the kernel reports it read: 384 B per batch of 64 sorted
-entries, 16 B per block of a fallback scan, 8 B per step.  roofline_full_scan
+bytes are what the kernel reports it read: 6 B per sorted entry, 16 B per
+block of a fallback scan, 8 B per step.  roofline_full_scan
 = the same for the full scan, timed on the same colony right after.
 cpu_baseline = the CPU oracle on a bounded sample of the same workload.
 """
@@ -50,11 +50,11 @@ def construct_bytes(n, m):
 
 def sorted_walk_bytes(stats, launches, n, m):
     """Algorithmic bytes of one sorted-walk construct launch from the kernel's
-    own counts: each batch is 64 entries of FP32 value + uint16 city, each
+    own counts: each sorted entry read is an FP32 value + a uint16 city, each
     fallback block one float4 row slice, and every step writes its tour entry
     and gathers its distance."""
-    batches, _, blocks = stats
-    return (batches * 64 * 6 + blocks * 16) / launches + m * (n - 1) * 8
+    entries, _, blocks = stats
+    return (entries * 6 + blocks * 16) / launches + m * (n - 1) * 8
 
 
 def counter_traffic(n, m, selection="adair"):
@@ -329,7 +329,7 @@ def main():
     if sorted_walk:
         stats = col.sorted_walk_stats()
         bytes_launch = sorted_walk_bytes(stats, args.steps, n, m)
-        walk = {"batches_per_step": stats[0] / (args.steps * ant_steps),
+        walk = {"entries_per_step": stats[0] / (args.steps * ant_steps),
                 "scanned_step_fraction": stats[1] / (args.steps * ant_steps),
                 "blocks_per_scanned_step": stats[2] / max(stats[1], 1)}
     else:

@@ -174,9 +174,10 @@ const float* aco_sorted_rows(const aco_ctx* ctx);
 const uint16_t* aco_sorted_cities(const aco_ctx* ctx);
 
 /* What the ACO_SELECT_ADAIR_SORTED constructs since the previous call (or
- * since aco_create) read, then resets the counts (blocks): out3[0] the batches
- * of 64 sorted entries read, summed over ants and steps; out3[1] the steps the
- * walk left to the scan; out3[2] the 4-city blocks those scans read.
+ * since aco_create) read, then resets the counts (blocks): out3[0] the sorted
+ * entries read (whole batches of the group width), summed over ants and steps;
+ * out3[1] the steps the walk left to the scan; out3[2] the 4-city blocks those
+ * scans read.
  * Errors: ACO_EINVAL for a NULL pointer. */
 aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3);
 
@@ -246,17 +247,19 @@ aco_status aco_set_selection(aco_ctx* ctx, int32_t selection);
  * aco_transition and aco_update also sort every row of the P they build (value
  * descending, city ascending; into workspace buffers), and aco_construct sorts
  * first if P has not been sorted yet.
- * A step then reads the row's entries in that order, 64 at a time, scoring
- * the unvisited ones.  It stops as soon as the smallest P of a batch is below
- * the best score found: no later city can reach that score.  If `batches`
- * batches (aco_set_sorted_walk) have not decided the step, it scans the row's
- * blocks (only the live ones under ACO_SCHED_G64_LIVE) as ACO_SELECT_ADAIR does.  Runs on a 64-lane schedule: ACO_SCHED_G64
- * (chosen by ACO_SCHED_AUTO) or ACO_SCHED_G64_LIVE; another forced schedule
- * makes aco_construct return ACO_EINVAL. */
+ * A step then reads the row's entries in that order, one per lane of the
+ * ant's group (G lanes: 16, 32 or 64 by schedule) at a time, scoring the
+ * unvisited ones.  It stops as soon as the smallest P of a batch is below the
+ * best score found: no later city can reach that score.  If 64 * walk entries
+ * (aco_set_sorted_walk) have not decided the step, it scans the row's blocks
+ * (only the live ones under a *_LIVE schedule) as ACO_SELECT_ADAIR does.  Any
+ * schedule runs it.  ACO_SCHED_AUTO takes no live list.  It takes the
+ * narrowest group that still leaves two wavefronts of ants per SIMD:
+ * 16 lanes from 8192 ants, 32 lanes from 4096 ants, else 64. */
 #define ACO_SORTED_WALK_MAX 256
 
-/* Batches of 64 sorted entries a step of ACO_SELECT_ADAIR_SORTED reads before
- * it falls back to the scan (default 8; 0 always scans).
+/* A step of ACO_SELECT_ADAIR_SORTED reads at most 64 * batches sorted entries
+ * before it falls back to the scan (default 8; 0 always scans).
  * Errors: ACO_EINVAL outside [0, ACO_SORTED_WALK_MAX]. */
 aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches);
 

@@ -357,13 +357,7 @@ aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) 
     if (aco_status st = bind_device(ctx)) return st;
     const bool sorted = ctx->selection == ACO_SELECT_ADAIR_SORTED;
     int32_t sched = ctx->schedule >= 0 ? ctx->schedule : aco::default_schedule(ctx->n);
-    if (sorted) {
-        if (ctx->schedule < 0) {
-            sched = ACO_SCHED_G64;
-        } else if (ctx->schedule != ACO_SCHED_G64 && ctx->schedule != ACO_SCHED_G64_LIVE) {
-            return fail(ACO_EINVAL, "aco_construct: the sorted walk needs a 64-lane schedule");
-        }
-    }
+    if (sorted && ctx->schedule < 0) sched = aco::sorted_default_schedule(m);
     if (ctx->selection == ACO_SELECT_ROULETTE && !aco::roulette_fits(ctx->n, sched))
         return fail(ACO_EINVAL,
                     "aco_construct: schedule %d cannot run the roulette wheel at n = %d", sched,

@@ -98,51 +98,6 @@ __device__ __forceinline__ int32_t group_uniform(int32_t v) {
     return v;
 }
 
-// ---- per-window output -----------------------------------------------------
-
-// Lane k of the calling lane's group (k the same on every lane of the wave).
-template <int G>
-__device__ __forceinline__ int32_t group_lane(int32_t v, int32_t k) {
-    if constexpr (G == kWave) {
-        return __builtin_amdgcn_readlane(v, k);
-    } else {
-        const int32_t g = (threadIdx.x & (kWave - 1)) / G;
-        int32_t r = 0;
-#pragma unroll
-        for (int32_t q = 0; q < kWave / G; ++q) {
-            const int32_t t = __builtin_amdgcn_readlane(v, q * G + k);
-            if (g == q) r = t;
-        }
-        return r;
-    }
-}
-
-// Write out a window of the tour: lane l of the group holds entry base + l
-// (l < cnt); `prev` is the entry before the window (-1 for the first).  Each
-// lane writes its entry and the successor / predecessor maps of the edge
-// that ends at it, and gathers that edge's length; the lengths are then
-// added to `len` one by one in tour order, so the FP64 sum is the
-// sequential one.  Runs once per G steps, which keeps scattered stores and
-// the random distance gathers out of the per-step chain.
-template <int G>
-__device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tour, int32_t ant,
-                                             int32_t base, int32_t cnt, int32_t win,
-                                             int32_t prev, int32_t gl, double& len) {
-    int32_t from = __shfl_up(win, 1, G);
-    if (gl == 0) from = prev;
-    float d = 0.0f;
-    if (gl < cnt) {
-        tour[base + gl] = win;
-        if (from >= 0) {
-            I.succ[static_cast<size_t>(from) * I.m_stride + ant] = win;
-            I.pred[static_cast<size_t>(win) * I.m_stride + ant] = from;
-            d = I.dist[static_cast<size_t>(from) * I.ld + win];
-        }
-    }
-    for (int32_t k = (prev < 0) ? 1 : 0; k < cnt; ++k)
-        len += static_cast<double>(__int_as_float(group_lane<G>(__float_as_int(d), k)));
-}
-
 // ---- roulette wheel helpers ----------------------------------------------
 
 __device__ __forceinline__ double f64_from_halves(uint32_t lo, uint32_t hi) {
@@ -319,25 +274,74 @@ __device__ __forceinline__ int32_t roulette_select(const InstanceView& I, const 
 // Build the tours of up to 64/G ants of one instance: group g of this wave
 // builds ant ant0 + g if g < nants.  `lds` is this wave's LDS region of
 // (64/G) * group_lds_words(n, LIVE) words.
-// Sorted walk of one step (G = 64): read the row's entries in descending P
-// order, 64 per batch, score the unvisited ones and keep each lane's best
-// (largest key, then smallest city).  Every deviate is below 1, so no city
-// scores above its P: once the smallest P of a batch is below the best score
-// so far, no later entry can reach it and the step is decided.  Returns the
-// city, or -1 if `walk` batches did not decide it.
+// ---- per-window output -----------------------------------------------------
+
+// Lane k of the calling lane's group (k the same on every lane of the wave).
+template <int G>
+__device__ __forceinline__ int32_t group_lane(int32_t v, int32_t k) {
+    if constexpr (G == kWave) {
+        return __builtin_amdgcn_readlane(v, k);
+    } else {
+        const int32_t g = (threadIdx.x & (kWave - 1)) / G;
+        int32_t r = 0;
+#pragma unroll
+        for (int32_t q = 0; q < kWave / G; ++q) {
+            const int32_t t = __builtin_amdgcn_readlane(v, q * G + k);
+            if (g == q) r = t;
+        }
+        return r;
+    }
+}
+
+// Write out a window of the tour: lane l of the group holds entry base + l
+// (l < cnt); `prev` is the entry before the window (-1 for the first).  Each
+// lane writes its entry and the successor / predecessor maps of the edge
+// that ends at it, and gathers that edge's length; the lengths are then
+// added to `len` one by one in tour order, so the FP64 sum is the
+// sequential one.  Runs once per G steps, which keeps scattered stores and
+// the random distance gathers out of the per-step chain.
+template <int G>
+__device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tour, int32_t ant,
+                                             int32_t base, int32_t cnt, int32_t win,
+                                             int32_t prev, int32_t gl, double& len) {
+    int32_t from = __shfl_up(win, 1, G);
+    if (gl == 0) from = prev;
+    float d = 0.0f;
+    if (gl < cnt) {
+        tour[base + gl] = win;
+        if (from >= 0) {
+            I.succ[static_cast<size_t>(from) * I.m_stride + ant] = win;
+            I.pred[static_cast<size_t>(win) * I.m_stride + ant] = from;
+            d = I.dist[static_cast<size_t>(from) * I.ld + win];
+        }
+    }
+    for (int32_t k = (prev < 0) ? 1 : 0; k < cnt; ++k)
+        len += static_cast<double>(__int_as_float(group_lane<G>(__float_as_int(d), k)));
+}
+
+// Sorted walk of one step of group g: read the row's entries in descending
+// P order, G per batch (one per lane), score the unvisited ones and keep each
+// lane's best (largest key, then smallest city).  Every deviate is below 1,
+// so no city scores above its P: once the smallest P of a batch is below the
+// best score so far, no later entry can reach it and the step is decided.
+// The walk reads at most 64 * walk entries.  Returns the city, or -1 if that
+// did not decide the step; `entries_read` counts the entries read.
+template <int G>
 __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cur,
-                                               const uint32_t* visited, int32_t lane, int32_t s,
-                                               int32_t ant, uint32_t& batches_read) {
+                                               const uint32_t* visited, int32_t gl, int32_t s,
+                                               int32_t ant, uint32_t& entries_read) {
     const size_t off = static_cast<size_t>(cur) * I.ld;
     const float* ps = I.Ps + off;
     const uint16_t* js = I.Js + off;
     int32_t best_key = -1;
     int32_t best_j = 0x7FFFFFFF;
-    const int32_t batches = min(I.walk, (I.n + kWave - 1) / kWave);
-    for (int32_t k = 0; k < batches; ++k) {
-        const int32_t pos = k * kWave + lane;
+    // 64 * walk is a multiple of G, so a batch is partial only when the limit
+    // is n itself; its empty lanes then read P = 0 and nothing follows them
+    const int32_t limit = min(64 * I.walk, I.n);
+    for (int32_t base = 0; base < limit; base += G) {
+        const int32_t pos = base + gl;
         float p = 0.0f;
-        if (pos < I.n) {
+        if (pos < limit) {
             p = ps[pos];
             const int32_t j = js[pos];
             if (!((visited[j >> 5] >> (j & 31)) & 1u)) {
@@ -354,11 +358,11 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                 }
             }
         }
-        ++batches_read;
-        const int32_t top = group_reduce<kWave, true>(best_key);
-        const float p_last = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p), kWave - 1));
+        entries_read += static_cast<uint32_t>(G);
+        const int32_t top = group_reduce<G, true>(best_key);
+        const float p_last = __int_as_float(group_lane<G>(__float_as_int(p), G - 1));
         if (top >= 0 && p_last < __int_as_float(top))
-            return group_reduce<kWave, false>(best_key == top ? best_j : 0x7FFFFFFF);
+            return group_reduce<G, false>(best_key == top ? best_j : 0x7FFFFFFF);
     }
     return -1;
 }
@@ -366,7 +370,6 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
 template <int G, bool LIVE, int SEL = kSelAdaIR>
 __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nants,
                                 uint32_t* __restrict__ lds) {
-    static_assert(SEL != kSelSorted || G == kWave, "the sorted walk runs with 64 lanes per ant");
     const int32_t lane = threadIdx.x & (kWave - 1);
     const int32_t g = lane / G;
     const int32_t gl = lane % G;
@@ -388,7 +391,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         for (int32_t i = gl; i < nblk; i += G) live[i] = static_cast<uint16_t>(i);
     }
     int32_t nlive = nblk;
-    uint32_t walk_batches = 0, scanned_steps = 0, scanned_blocks = 0;
+    uint32_t walk_entries = 0, scanned_steps = 0, scanned_blocks = 0;
     __builtin_amdgcn_wave_barrier();
 
     // Start city (Sec. 2.2 initialization): word 0 of counter (0, 0, ant, iter).
@@ -406,7 +409,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         int32_t walked = -1;
         if constexpr (SEL == kSelSorted) {
             if (s > 0) {
-                walked = group_uniform<G>(sorted_walk(I, cur, visited, gl, s, ant, walk_batches));
+                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, ant, walk_entries));
                 if (walked < 0) {
                     ++scanned_steps;
                     scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
@@ -497,7 +500,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         I.lengths[ant] = static_cast<float>(len);
         if constexpr (SEL == kSelSorted) {
             if (I.walk_stats) {
-                atomicAdd(I.walk_stats + 0, static_cast<unsigned long long>(walk_batches));
+                atomicAdd(I.walk_stats + 0, static_cast<unsigned long long>(walk_entries));
                 atomicAdd(I.walk_stats + 1, static_cast<unsigned long long>(scanned_steps));
                 atomicAdd(I.walk_stats + 2, static_cast<unsigned long long>(scanned_blocks));
             }
@@ -532,11 +535,8 @@ hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipSt
         hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelRoulette>), grid, dim3(kWave), lds,
                            stream, I, m);
     } else if (selection == kSelSorted) {
-        if constexpr (G == kWave)
-            hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelSorted>), grid, dim3(kWave), lds,
-                               stream, I, m);
-        else
-            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelSorted>), grid, dim3(kWave), lds,
+                           stream, I, m);
     } else {
         hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelAdaIR>), grid, dim3(kWave), lds,
                            stream, I, m);
@@ -626,6 +626,13 @@ int32_t default_schedule(int32_t n) {
     if (nblk <= 32) return kSched32;
     if (nblk <= 64) return kSched64;
     return kSched64Live;
+}
+
+int32_t sorted_default_schedule(int32_t m) {
+    // at least two wavefronts of ants per SIMD (1024 SIMDs)
+    if (m >= 8192) return kSched16;
+    if (m >= 4096) return kSched32;
+    return kSched64;
 }
 
 size_t wave_lds_bytes(int32_t n, int32_t sched) {

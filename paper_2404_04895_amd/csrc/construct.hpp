@@ -21,7 +21,7 @@ struct InstanceView {
     const float* Ps;     // n x ld rows of P sorted by value (sorted walk only)
     const uint16_t* Js;  // n x ld city of each sorted entry
     int32_t walk;        // sorted batches per step before the scan
-    unsigned long long* walk_stats;  // sorted walk: batches read, steps scanned, blocks scanned
+    unsigned long long* walk_stats;  // sorted walk: entries read, steps scanned, blocks scanned
 };
 
 // Per-step selection rules (the ACO_SELECT_* codes of the C ABI).
@@ -49,6 +49,11 @@ int32_t schedule_lanes(int32_t sched);
 bool schedule_live(int32_t sched);
 bool schedule_valid(int32_t sched);
 int32_t default_schedule(int32_t n);
+// Schedule of the sorted walk for m ants when none is forced: no live list
+// (the walk decides almost every step), and the narrowest group (fewest
+// instructions per ant-step) that still leaves two wavefronts per SIMD to
+// hide the latency of each step's chain.
+int32_t sorted_default_schedule(int32_t m);
 size_t wave_lds_bytes(int32_t n, int32_t sched);
 
 // ---- batched engine --------------------------------------------------------

@@ -38,7 +38,7 @@ struct Buffers {
     uint32_t* flags;    // 4 validation flags
     float* Ps;          // n x ld: each row of P sorted by value, descending
     uint16_t* Js;       // n x ld: the city of each entry of Ps
-    unsigned long long* walk_stats;  // 3: sorted batches read, steps scanned, blocks scanned
+    unsigned long long* walk_stats;  // 3: sorted entries read, steps scanned, blocks scanned
 };
 
 struct Layout {
@@ -68,9 +68,9 @@ hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, 
 hipError_t launch_copy_padded(const float* src_dense, float* dst, int32_t n, int32_t ld,
                               hipStream_t stream);
 // selection: ACO_SELECT_* (the roulette wheel needs roulette_fits; the sorted
-// walk needs the sorted rows in B.Ps / B.Js and a 64-lane schedule).
-// walk: batches of 64 sorted entries a step reads before it falls back to
-// the scan (ACO_SELECT_ADAIR_SORTED only).
+// walk needs the sorted rows in B.Ps / B.Js).
+// walk: a step reads at most 64 * walk sorted entries before it falls back
+// to the scan (ACO_SELECT_ADAIR_SORTED only).
 hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
                             uint64_t seed, uint32_t iter, int32_t sched, int32_t selection,
                             int32_t walk, hipStream_t stream);

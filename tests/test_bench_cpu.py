@@ -24,8 +24,8 @@ def test_sorted_walk_bytes():
     import bench
     n, m = 100, 10
     steps = m * (n - 1)
-    # one batch per step, no fallback, over two launches
-    assert bench.sorted_walk_bytes((2 * steps, 0, 0), 2, n, m) == steps * 384 + steps * 8
-    # every step falls back and scans all 25 blocks after 4 batches
-    got = bench.sorted_walk_bytes((4 * steps, steps, 25 * steps), 1, n, m)
-    assert got == steps * (4 * 384 + 25 * 16 + 8)
+    # 64 entries per step, no fallback, over two launches
+    assert bench.sorted_walk_bytes((2 * 64 * steps, 0, 0), 2, n, m) == steps * 384 + steps * 8
+    # every step falls back and scans all 25 blocks after 256 entries
+    got = bench.sorted_walk_bytes((256 * steps, steps, 25 * steps), 1, n, m)
+    assert got == steps * (256 * 6 + 25 * 16 + 8)

@@ -63,22 +63,28 @@ def test_sorted_walk_bit_exact(n, m):
     o_tours, o_len = oracle.construct(P, D, seed, it, np.arange(m))
     col.set_selection("adair-sorted")
     steps = m * (n - 1)
-    for sched, walk in (("auto", 4), (3, 2), (4, 2), (3, 0), (4, 0), (4, 1), (3, 8), (3, 256)):
+    lanes = {0: 16, 1: 32, 2: 32, 3: 64, 4: 64}
+    auto = 3  # 64 lanes below 4096 ants
+    for sched, walk in (("auto", 4), (3, 2), (4, 2), (0, 2), (1, 3), (2, 2), (3, 0), (1, 0),
+                        (4, 1), (0, 1), (3, 8), (1, 256)):
         if sched != "auto":
             col.set_schedule(sched)
+        G = lanes[auto if sched == "auto" else sched]
         col.set_sorted_walk(walk)
         col.construct(m, seed, it)
         col.sync()
         assert np.array_equal(col.tours(m).cpu().numpy(), o_tours), (sched, walk)
         assert np.array_equal(col.lengths(m).cpu().numpy().view(np.uint32), o_len.view(np.uint32))
-        batches, scanned, blocks = col.sorted_walk_stats()
-        nb = -(-n // 64)
+        entries, scanned, blocks = col.sorted_walk_stats()
+        limit = min(64 * walk, n)
+        most = -(-limit // G) * G  # whole batches up to the limit
         if walk == 0:
-            assert (batches, scanned) == (0, steps)
+            assert (entries, scanned) == (0, steps)
         else:
             # every step reads at least one batch; a step that falls to the scan read all it may
-            assert steps <= batches <= steps * min(walk, nb)
-            assert batches >= steps + scanned * (min(walk, nb) - 1)
+            assert entries % G == 0
+            assert steps * G <= entries <= steps * most
+            assert entries >= steps * G + scanned * (most - G)
         assert 0 <= scanned <= steps
         assert scanned <= blocks <= scanned * ((n + 3) // 4)
         if n <= 300 or walk == 256:
@@ -142,10 +148,6 @@ def test_sorted_walk_free_run_and_rejections():
         col.set_sorted_walk(-1)
     with pytest.raises(AcoError):
         col.set_sorted_walk(257)
-    col.set_schedule(1)  # 32 lanes: the walk needs 64
-    col.transition(1.0)
-    with pytest.raises(AcoError):
-        col.construct(m, 1, 0)
     col.close()
 
 
