@@ -63,7 +63,7 @@ def lib():
                                             ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_int32,
                                             ctypes.c_float, ctypes.c_float, ctypes.c_int32,
-                                            ctypes.c_uint64,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_uint64,
                                             ctypes.c_uint32, ctypes.c_int32, _f32p, _f32p,
                                             _i32p, _f32p, _i32p, _f32p]),
             "oracle_tsp_exact": (ctypes.c_double, [_f32p, ctypes.c_int32, _i32p]),
@@ -81,6 +81,7 @@ def lib():
             "oracle_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double]),
+            "oracle_clamp": (None, [_f32p, ctypes.c_int32, ctypes.c_float, ctypes.c_float]),
             "oracle_roulette_deviate": (ctypes.c_float, [ctypes.c_uint64, ctypes.c_uint32,
                                                          ctypes.c_uint32, ctypes.c_uint32]),
             "oracle_select_roulette": (ctypes.c_int32, [_f32p, _u8p, ctypes.c_int32,
@@ -186,6 +187,13 @@ def construct(P, dist, seed, t, ants, *, selection="adair"):
     return tours, lengths
 
 
+def clamp(tau, tau_min, tau_max):
+    """MAX-MIN bounds applied to a copy of tau (off the diagonal)."""
+    tau = np.array(tau, dtype=np.float32, copy=True, order="C")
+    lib().oracle_clamp(_ptr(tau, ctypes.c_float), tau.shape[0], tau_min, tau_max)
+    return tau
+
+
 def roulette_deviate(seed, t, a, s):
     return lib().oracle_roulette_deviate(seed, t, a, s)
 
@@ -253,7 +261,7 @@ def gamma(t, T, gamma_max, gamma_min):
 
 def run(dist, m, alpha, beta, rho, Q, seed, iters, *, m_max=None, elite_k=0,
         gamma_max=1.5, gamma_min=1.0, tau0=1.0, iter0=0, eta=None, tau=None,
-        selection="adair"):
+        selection="adair", tau_min=0.0, tau_max=float("inf")):
     """Whole run; returns dict(tau, P, best_tour, best_len, best_iter, S, iter_best)."""
     n = dist.shape[0]
     dist = _c(dist, np.float32)
@@ -269,8 +277,8 @@ def run(dist, m, alpha, beta, rho, Q, seed, iters, *, m_max=None, elite_k=0,
     iter_best = np.zeros(max(iters, 1), np.float32)
     S = lib().oracle_run(_ptr(dist, ctypes.c_float), _ptr(eta_c, ctypes.c_float), n, m,
                          m if m_max is None else m_max, alpha, beta, rho, Q, elite_k,
-                         gamma_max, gamma_min, {"adair": 0, "roulette": 1}[selection], seed,
-                         iter0, iters, _ptr(tau, ctypes.c_float),
+                         gamma_max, gamma_min, {"adair": 0, "roulette": 1}[selection],
+                         tau_min, tau_max, seed, iter0, iters, _ptr(tau, ctypes.c_float),
                          _ptr(P, ctypes.c_float), _ptr(best_tour, ctypes.c_int32),
                          ctypes.byref(best_len), ctypes.byref(best_iter),
                          _ptr(iter_best, ctypes.c_float))

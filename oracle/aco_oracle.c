@@ -384,6 +384,21 @@ ORACLE_API void oracle_evaporate(float* tau, const int64_t* delta, int32_t n, fl
     }
 }
 
+/* MAX-MIN bounds on the pheromone (the MAX-MIN Ant System of Stuetzle and
+ * Hoos; not in the paper): after evaporation and deposit every off-diagonal
+ * tau is clamped into [tau_min, tau_max].  tau_min = 0 and tau_max = +inf
+ * leave tau unchanged. */
+ORACLE_API void oracle_clamp(float* tau, int32_t n, float tau_min, float tau_max) {
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            size_t ij = (size_t)i * (size_t)n + (size_t)j;
+            if (tau[ij] < tau_min) tau[ij] = tau_min;
+            if (tau[ij] > tau_max) tau[ij] = tau_max;
+        }
+    }
+}
+
 /* Cosine annealing of gamma (reading R7), from gamma_max at t = 0 down to
  * gamma_min at t = T-1, rounded to FP32. */
 ORACLE_API float oracle_gamma(int32_t t, int32_t T, float gamma_max, float gamma_min) {
@@ -399,13 +414,14 @@ ORACLE_API float oracle_gamma(int32_t t, int32_t T, float gamma_max, float gamma
  * constructs (Sec. 2.2, 2.4), the best-so-far is kept (smallest length, ties
  * to the earlier iteration then the smaller ant), the elite deposit
  * (Sec. 2.3) and evaporation update tau, and P is rebuilt with gamma_{t+1}
- * (Sec. 2.1).  roulette != 0 selects by the Roulette Wheel instead of AdaIR.
+ * (Sec. 2.1).  roulette != 0 selects by the Roulette Wheel instead of AdaIR;
+ * tau is clamped into [tau_min, tau_max] after each update.
  * tau (n x n) is in/out; P (n x n) is out. */
 ORACLE_API int32_t oracle_run(const float* dist, const float* eta, int32_t n, int32_t m,
                               int32_t m_max, float alpha, float beta, float rho, float Q,
                               int32_t elite_k, float gamma_max, float gamma_min,
-                              int32_t roulette, uint64_t seed, uint32_t iter0, int32_t iters,
-                              float* tau,
+                              int32_t roulette, float tau_min, float tau_max, uint64_t seed,
+                              uint32_t iter0, int32_t iters, float* tau,
                               float* P, int32_t* best_tour, float* best_len,
                               int32_t* best_iter, float* iter_best_len) {
     size_t nn = (size_t)n * (size_t)n;
@@ -444,6 +460,7 @@ ORACLE_API int32_t oracle_run(const float* dist, const float* eta, int32_t n, in
         oracle_elite(lengths, m, elite_k, elite);
         oracle_deposit(tours, lengths, elite, m, n, Q, S, delta);
         oracle_evaporate(tau, delta, n, rho, S);
+        oracle_clamp(tau, n, tau_min, tau_max);
         oracle_transition(tau, dist, eta, n, alpha, beta,
                           oracle_gamma(it + 1, iters, gamma_max, gamma_min), P);
     }
