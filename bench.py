@@ -251,6 +251,11 @@ def main():
                     help="skip the full-scan reference timing after the sorted walk")
     ap.add_argument("--schedule", type=int, default=None,
                     help="construct schedule code (ACO_SCHED_*); default: by size")
+    ap.add_argument("--elite-k", type=int, default=None,
+                    help="deposit from the k shortest tours only (the paper uses n/10)")
+    ap.add_argument("--tau-min", type=float, default=0.0, help="MAX-MIN lower bound on tau")
+    ap.add_argument("--tau-max", type=float, default=float("inf"),
+                    help="MAX-MIN upper bound on tau")
     ap.add_argument("--walk", type=int, default=None,
                     help="sorted batches per step before the scan (adair-sorted)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -279,8 +284,10 @@ def main():
     D = w.dist(args.seed)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    elite_k = w.elite_k if args.elite_k is None else args.elite_k
     col = Colony(torch.from_numpy(D).to(dev), w.alpha, w.beta, w.rho, w.Q, m, tau0=w.tau0,
-                 elite_k=w.elite_k, gamma_max=w.gamma_max, gamma_min=w.gamma_min)
+                 elite_k=elite_k, gamma_max=w.gamma_max, gamma_min=w.gamma_min)
+    col.set_tau_bounds(args.tau_min, args.tau_max)
     col.set_selection(args.selection)
     if args.walk is not None:
         col.set_sorted_walk(args.walk)
@@ -375,7 +382,8 @@ def main():
                    "rho": w.rho, "Q": w.Q, "cities": "%s, %d Gaussians sigma %g" % (
                        w.family, w.clusters, w.sigma) if w.family != "uniform" else "uniform",
                    "gamma": [w.gamma_max, w.gamma_min], "seed": args.seed,
-                   "selection": args.selection},
+                   "selection": args.selection, "elite_k": elite_k,
+                   "tau_bounds": [args.tau_min, args.tau_max]},
         "roofline": {"bound": "hbm",
                      "kernel": "construct_kernel (sorted walk)" if sorted_walk else "construct_kernel",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

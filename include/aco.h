@@ -103,6 +103,15 @@ aco_status aco_set_stream(aco_ctx* ctx, void* hip_stream);
  * Errors: ACO_EINVAL for tau0 <= 0, elite_k < 0 or > m_max, gamma <= 0. */
 aco_status aco_set_params(aco_ctx* ctx, const aco_params* params);
 
+/* MAX-MIN pheromone bounds (the MAX-MIN Ant System of Stuetzle and Hoos; not
+ * in the paper): from the next aco_update on, every off-diagonal tau is clamped
+ * into [tau_min, tau_max] right after evaporation and deposit (on the rounded
+ * FP32 value), and P is built from the clamped tau.  tau0 is not clamped.
+ * Defaults 0 and +INFINITY: no bounds.  Single-instance contexts only.
+ * Errors: ACO_EINVAL unless 0 <= tau_min <= tau_max, tau_min finite, tau_max > 0
+ * (tau_max may be +INFINITY). */
+aco_status aco_set_tau_bounds(aco_ctx* ctx, float tau_min, float tau_max);
+
 /* Replace the heuristic eta of Eq. (1) (default 1/d) by a caller matrix.
  *   eta_dev  device pointer, n x n FP32 dense (leading dim n), or NULL to
  *            return to 1/d.

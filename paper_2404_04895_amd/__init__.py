@@ -150,6 +150,10 @@ class Colony:
                 "adair-sorted": _native.SELECT_ADAIR_SORTED}[selection]
         check(lib().aco_set_selection(self._ctx, code), "aco_set_selection")
 
+    def set_tau_bounds(self, tau_min: float = 0.0, tau_max: float = float("inf")):
+        """MAX-MIN bounds on tau after each update (0, inf: none)."""
+        check(lib().aco_set_tau_bounds(self._ctx, tau_min, tau_max), "aco_set_tau_bounds")
+
     def set_sorted_walk(self, batches: int):
         """Batches of 64 sorted entries a step reads before it scans (adair-sorted)."""
         check(lib().aco_set_sorted_walk(self._ctx, batches), "aco_set_sorted_walk")

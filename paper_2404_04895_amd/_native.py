@@ -72,6 +72,7 @@ SIGNATURES = {
     "aco_uniforms": (_i32, [_u64, _u32, _u32, _u32, _i32, _vp, _vp]),
     "aco_set_schedule": (_i32, [_vp, _i32]),
     "aco_set_selection": (_i32, [_vp, _i32]),
+    "aco_set_tau_bounds": (_i32, [_vp, _f32, _f32]),
     "aco_set_sorted_walk": (_i32, [_vp, _i32]),
     "aco_batch_workspace_bytes": (ctypes.c_size_t, [_vp, _vp, _i32]),
     "aco_batch_create": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp, _vp,

@@ -31,6 +31,8 @@ struct aco_ctx {
     int32_t selection = ACO_SELECT_ADAIR;  // per-step selection rule (ACO_SELECT_*)
     int32_t walk = 8;          // sorted batches a step reads before the scan
     bool rows_sorted = false;  // Ps / Js hold the sorted rows of the current P
+    float tau_min = 0.0f;      // MAX-MIN bounds on tau after each update
+    float tau_max = INFINITY;
 };
 
 namespace {
@@ -327,6 +329,16 @@ aco_status aco_set_selection(aco_ctx* ctx, int32_t selection) {
     return ACO_OK;
 }
 
+aco_status aco_set_tau_bounds(aco_ctx* ctx, float tau_min, float tau_max) {
+    if (aco_status st = check_ctx(ctx)) return st;
+    if (!(tau_min >= 0.0f) || !isfinite(tau_min) || !(tau_max > 0.0f) || isnan(tau_max) ||
+        tau_min > tau_max)
+        return fail(ACO_EINVAL, "aco_set_tau_bounds: need 0 <= tau_min <= tau_max, tau_max > 0");
+    ctx->tau_min = tau_min;
+    ctx->tau_max = tau_max;
+    return ACO_OK;
+}
+
 aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches) {
     if (aco_status st = check_ctx(ctx)) return st;
     if (batches < 0 || batches > ACO_SORTED_WALK_MAX)
@@ -342,7 +354,8 @@ aco_status aco_transition(aco_ctx* ctx, float gamma) {
     if (!finite_positive(gamma)) return fail(ACO_EINVAL, "aco_transition: gamma <= 0");
     if (aco_status st = bind_device(ctx)) return st;
     ACO_HIP(aco::launch_rows(ctx->buf, ctx->n, ctx->ld, 0, ctx->m_max, false, ctx->eta_active,
-                             ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma, ctx->stream),
+                             ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma, ctx->tau_min,
+                             ctx->tau_max, ctx->stream),
             "transition");
     ctx->have_P = true;
     ctx->rows_sorted = false;
@@ -383,7 +396,8 @@ aco_status aco_update(aco_ctx* ctx, float gamma_next) {
                                         ctx->stream),
             "deposit weights");
     ACO_HIP(aco::launch_rows(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, true, ctx->eta_active,
-                             ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma_next, ctx->stream),
+                             ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma_next, ctx->tau_min,
+                             ctx->tau_max, ctx->stream),
             "update rows");
     ctx->have_tours = false;
     ctx->have_P = true;

@@ -89,9 +89,11 @@ hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, 
 hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
                        hipStream_t stream);
 hipError_t launch_clear_best(BestRecord* best, int32_t count, hipStream_t stream);
+// tau_min, tau_max: MAX-MIN bounds applied after the update (0, +inf: none).
 hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
                        bool apply_deposit, bool use_eta, float alpha, float beta, float rho,
-                       int32_t S, float gamma, hipStream_t stream);
+                       int32_t S, float gamma, float tau_min, float tau_max,
+                       hipStream_t stream);
 hipError_t launch_uniforms(uint64_t seed, uint32_t iter, uint32_t ant, uint32_t step,
                            int32_t count, float* out, hipStream_t stream);
 hipError_t prepare_kernels();

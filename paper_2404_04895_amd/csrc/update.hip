@@ -108,6 +108,7 @@ struct RowArgs {
     int32_t n, ld, i, m;
     int32_t apply_deposit;
     double keep, unit, alpha, beta, gamma;
+    float tau_min, tau_max;  // MAX-MIN bounds applied after the update (0, +inf: none)
 };
 
 template <int T>
@@ -133,6 +134,7 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
         if (a.apply_deposit) {
             const double add = static_cast<double>(static_cast<int64_t>(acc[j])) * a.unit;
             t = static_cast<float>(__fma_rn(a.keep, static_cast<double>(t), add));
+            t = fminf(fmaxf(t, a.tau_min), a.tau_max);
             a.tau[j] = t;
         }
         const double ln_eta = a.eta ? log(static_cast<double>(a.eta[j]))
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(
     const float* __restrict__ eta, int32_t n, int32_t ld, int32_t m, int32_t m_max,
     const int32_t* __restrict__ succ, const int32_t* __restrict__ pred,
     const int64_t* __restrict__ weight, int32_t apply_deposit, double keep, double unit,
-    double alpha, double beta, double gamma) {
+    double alpha, double beta, double gamma, float tau_min, float tau_max) {
     extern __shared__ double lnw[];
     __shared__ double red[ACO_LDS_ROW_MAX / 64];  // wave maxima, then chunk sums
     const int32_t i = blockIdx.x;
@@ -181,6 +183,8 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(
     a.alpha = alpha;
     a.beta = beta;
     a.gamma = gamma;
+    a.tau_min = tau_min;
+    a.tau_max = tau_max;
     update_row<kRowThreads>(a, lnw, red);
 }
 
@@ -382,6 +386,8 @@ __global__ __launch_bounds__(64) void batch_rows_kernel(const BatchInstance* __r
     a.alpha = alpha;
     a.beta = beta;
     a.gamma = static_cast<double>(*gamma_ptr);
+    a.tau_min = 0.0f;
+    a.tau_max = INFINITY;
     update_row<64>(a, lnw, nullptr);
 }
 
@@ -485,13 +491,14 @@ hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
 
 hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,
                        bool apply_deposit, bool use_eta, float alpha, float beta, float rho,
-                       int32_t S, float gamma, hipStream_t stream) {
+                       int32_t S, float gamma, float tau_min, float tau_max,
+                       hipStream_t stream) {
     const size_t lds = sizeof(double) * static_cast<size_t>(ld);
     hipLaunchKernelGGL(row_kernel, dim3(n), dim3(kRowThreads), lds, stream, B.tau, B.P, B.dist,
                        use_eta ? B.eta : nullptr, n, ld, m, m_max, B.succ, B.pred, B.weight,
                        apply_deposit ? 1 : 0, 1.0 - static_cast<double>(rho), ldexp(1.0, -S),
                        static_cast<double>(alpha), static_cast<double>(beta),
-                       static_cast<double>(gamma));
+                       static_cast<double>(gamma), tau_min, tau_max);
     return hipGetLastError();
 }
 
