@@ -319,6 +319,32 @@ __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tou
         len += static_cast<double>(__int_as_float(group_lane<G>(__float_as_int(d), k)));
 }
 
+// The first batch of one row's sorted entries, loaded one step ahead for
+// the city most likely to be taken next (`city` is -1 when there is none).
+struct SortedSpec {
+    int32_t city;  // same on every lane of the group
+    float p;       // this lane's entry of the batch
+    int32_t j;
+};
+
+// v of the first lane of the calling lane's group whose bit is set in
+// `ballot`, or -1 if none is set; the lane indices are wave-uniform, so this
+// is scalar work and readlanes.
+template <int G>
+__device__ __forceinline__ int32_t group_first(uint64_t ballot, int32_t v) {
+    const int32_t g = (threadIdx.x & (kWave - 1)) / G;
+    int32_t r = -1;
+#pragma unroll
+    for (int32_t q = 0; q < kWave / G; ++q) {
+        const uint64_t bits = (G == kWave) ? ballot : ((ballot >> (q * G)) & ((1ull << (G & 63)) - 1ull));
+        if (bits) {
+            const int32_t t = __builtin_amdgcn_readlane(v, q * G + __builtin_ctzll(bits));
+            if (g == q) r = t;
+        }
+    }
+    return r;
+}
+
 // Sorted walk of one step of group g: read the row's entries in descending
 // P order, G per batch (one per lane), score the unvisited ones and keep each
 // lane's best (largest key, then smallest city).  Every deviate is below 1,
@@ -326,10 +352,17 @@ __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tou
 // best score so far, no later entry can reach it and the step is decided.
 // The walk reads at most 64 * walk entries.  Returns the city, or -1 if that
 // did not decide the step; `entries_read` counts the entries read.
+//
+// The first unvisited entry of the first batch is the likeliest next city
+// (it has the largest P left).  The first batch of its row is loaded as soon
+// as that entry is known, while the deviates are still being drawn; the next
+// step uses it if that city is taken.  Only where the data comes from
+// changes, not the result.
 template <int G>
 __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cur,
                                                const uint32_t* visited, int32_t gl, int32_t s,
-                                               int32_t ant, uint32_t& entries_read) {
+                                               int32_t ant, uint32_t& entries_read,
+                                               SortedSpec& spec) {
     const size_t off = static_cast<size_t>(cur) * I.ld;
     const float* ps = I.Ps + off;
     const uint16_t* js = I.Js + off;
@@ -338,24 +371,40 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
     // 64 * walk is a multiple of G, so a batch is partial only when the limit
     // is n itself; its empty lanes then read P = 0 and nothing follows them
     const int32_t limit = min(64 * I.walk, I.n);
+    const bool ahead = spec.city == cur;
     for (int32_t base = 0; base < limit; base += G) {
         const int32_t pos = base + gl;
         float p = 0.0f;
+        int32_t j = -1;
         if (pos < limit) {
-            p = ps[pos];
-            const int32_t j = js[pos];
-            if (!((visited[j >> 5] >> (j & 31)) & 1u)) {
-                const PhiloxOut r = philox10_block(static_cast<uint32_t>(j >> 2),
-                                                   static_cast<uint32_t>(s),
-                                                   static_cast<uint32_t>(ant), I.iter, I.key0,
-                                                   I.key1);
-                const int32_t q = j & 3;
-                const uint32_t w = q == 0 ? r.w0 : (q == 1 ? r.w1 : (q == 2 ? r.w2 : r.w3));
-                const int32_t key = score_key(p, w, 0u);
-                if (key > best_key || (key == best_key && j < best_j)) {
-                    best_key = key;
-                    best_j = j;
-                }
+            if (base == 0 && ahead) {
+                p = spec.p;
+                j = spec.j;
+            } else {
+                p = ps[pos];
+                j = js[pos];
+            }
+        }
+        const bool cand = j >= 0 && !((visited[j >> 5] >> (j & 31)) & 1u);
+        if (base == 0) {
+            spec.city = group_first<G>(__ballot(cand), j);
+            if (spec.city >= 0 && gl < limit) {
+                const size_t next = static_cast<size_t>(spec.city) * I.ld + gl;
+                spec.p = I.Ps[next];
+                spec.j = I.Js[next];
+            }
+        }
+        if (cand) {
+            const PhiloxOut r = philox10_block(static_cast<uint32_t>(j >> 2),
+                                               static_cast<uint32_t>(s),
+                                               static_cast<uint32_t>(ant), I.iter, I.key0,
+                                               I.key1);
+            const int32_t q = j & 3;
+            const uint32_t w = q == 0 ? r.w0 : (q == 1 ? r.w1 : (q == 2 ? r.w2 : r.w3));
+            const int32_t key = score_key(p, w, 0u);
+            if (key > best_key || (key == best_key && j < best_j)) {
+                best_key = key;
+                best_j = j;
             }
         }
         entries_read += static_cast<uint32_t>(G);
@@ -392,6 +441,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     }
     int32_t nlive = nblk;
     uint32_t walk_entries = 0, scanned_steps = 0, scanned_blocks = 0;
+    SortedSpec spec{-1, 0.0f, 0};
     __builtin_amdgcn_wave_barrier();
 
     // Start city (Sec. 2.2 initialization): word 0 of counter (0, 0, ant, iter).
@@ -409,7 +459,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         int32_t walked = -1;
         if constexpr (SEL == kSelSorted) {
             if (s > 0) {
-                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, ant, walk_entries));
+                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, ant, walk_entries, spec));
                 if (walked < 0) {
                     ++scanned_steps;
                     scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
