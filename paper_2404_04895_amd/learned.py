@@ -12,6 +12,7 @@ out of its iteration budget), judged by the best tour length.
 
     python -m paper_2404_04895_amd.learned train [--out FILE]
     python -m paper_2404_04895_amd.learned evaluate [--weights FILE]
+    python -m paper_2404_04895_amd.learned profile [--reps K]
 """
 import argparse
 import json
@@ -231,7 +232,8 @@ def evaluation_instances(count=10, n=2000, clusters=30, sigma=0.015, seed0=2000)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["train", "validate", "evaluate"])
+    ap.add_argument("mode", choices=["train", "validate", "evaluate", "profile"])
+    ap.add_argument("--reps", type=int, default=6, help="inference repetitions (profile)")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--steps", type=int, default=20000)
@@ -262,6 +264,20 @@ def main():
                        "validation_mean_gap": {str(k): v for k, v in means.items()}}, f,
                       indent=1)
         print("chose kappa %.2f" % kappa, flush=True)
+    elif args.mode == "profile":
+        # inference alone (ranks, features, network, eta) on the first held-out instance
+        import torch
+        master = load_weights(args.weights)
+        assert master is not None, "no weights at " + args.weights
+        kappa, lam = heuristic_config(args.weights)
+        dev = torch.from_numpy(evaluation_instances(1)[0]).cuda()
+        for _ in range(args.reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, bad = learned_eta(dev, master, kappa, lam)
+            torch.cuda.synchronize()
+            print("inference %.3f ms, %d non-finite" % ((time.perf_counter() - t0) * 1e3, bad),
+                  flush=True)
     else:
         master = load_weights(args.weights)
         assert master is not None, "no weights at " + args.weights
