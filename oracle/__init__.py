@@ -81,6 +81,9 @@ def lib():
             "oracle_adam_step": (None, [_f64p, _f64p, _f64p, _f64p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double]),
+            "oracle_transition_rows": (None, [_f32p, _f32p, _f32p, ctypes.c_int32, ctypes.c_float,
+                                              ctypes.c_float, ctypes.c_float, _i32p,
+                                              ctypes.c_int32, _f32p]),
             "oracle_clamp": (None, [_f32p, ctypes.c_int32, ctypes.c_float, ctypes.c_float]),
             "oracle_roulette_deviate": (ctypes.c_float, [ctypes.c_uint64, ctypes.c_uint32,
                                                          ctypes.c_uint32, ctypes.c_uint32]),
@@ -148,6 +151,21 @@ def transition(tau, dist, alpha, beta, gamma, eta=None):
                             _ptr(eta_c, ctypes.c_float), n, alpha, beta, gamma,
                             _ptr(P, ctypes.c_float))
     return P
+
+
+def transition_rows(tau, dist, alpha, beta, gamma, rows, eta=None):
+    """Rows `rows` of the transition matrix (len(rows) x n)."""
+    n = dist.shape[0]
+    tau = _c(tau, np.float32)
+    dist = _c(dist, np.float32)
+    eta_c = None if eta is None else _c(eta, np.float32)
+    rows = _c(rows, np.int32)
+    out = np.zeros((rows.shape[0], n), np.float32)
+    lib().oracle_transition_rows(_ptr(tau, ctypes.c_float), _ptr(dist, ctypes.c_float),
+                                 _ptr(eta_c, ctypes.c_float), n, alpha, beta, gamma,
+                                 _ptr(rows, ctypes.c_int32), rows.shape[0],
+                                 _ptr(out, ctypes.c_float))
+    return out
 
 
 def select(row, visited, seed, t, a, s):

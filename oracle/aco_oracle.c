@@ -120,32 +120,44 @@ ORACLE_API int32_t oracle_start_city(uint64_t seed, uint32_t t, uint32_t a, int3
 /* shifted by its maximum before exponentiation (same quotient).  The sum    */
 /* runs over k in ascending order.                                          */
 /* ------------------------------------------------------------------------ */
+static void transition_row(const float* tau, const float* dist, const float* eta, int32_t n,
+                           float alpha, float beta, float gamma, int32_t i, float* P_row) {
+    double* lnw = (double*)malloc(sizeof(double) * (size_t)n);
+    double row_max = -INFINITY;
+    for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        size_t ij = (size_t)i * (size_t)n + (size_t)j;
+        double ln_eta = eta ? log((double)eta[ij]) : -log((double)dist[ij]);
+        lnw[j] = (double)alpha * log((double)tau[ij]) + (double)beta * ln_eta;
+        if (lnw[j] > row_max) row_max = lnw[j];
+    }
+    double sum = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        sum += exp(lnw[j] - row_max);
+    }
+    double ln_sum = row_max + log(sum);
+    for (int32_t j = 0; j < n; ++j)
+        P_row[j] = (j == i) ? 0.0f : (float)exp((lnw[j] - ln_sum) / (double)gamma);
+    free(lnw);
+}
+
 ORACLE_API void oracle_transition(const float* tau, const float* dist, const float* eta,
                                   int32_t n, float alpha, float beta, float gamma,
                                   float* P) {
 #pragma omp parallel for schedule(static)
-    for (int32_t i = 0; i < n; ++i) {
-        double* lnw = (double*)malloc(sizeof(double) * (size_t)n);
-        double row_max = -INFINITY;
-        for (int32_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            size_t ij = (size_t)i * (size_t)n + (size_t)j;
-            double ln_eta = eta ? log((double)eta[ij]) : -log((double)dist[ij]);
-            lnw[j] = (double)alpha * log((double)tau[ij]) + (double)beta * ln_eta;
-            if (lnw[j] > row_max) row_max = lnw[j];
-        }
-        double sum = 0.0;
-        for (int32_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            sum += exp(lnw[j] - row_max);
-        }
-        double ln_sum = row_max + log(sum);
-        for (int32_t j = 0; j < n; ++j) {
-            size_t ij = (size_t)i * (size_t)n + (size_t)j;
-            P[ij] = (j == i) ? 0.0f : (float)exp((lnw[j] - ln_sum) / (double)gamma);
-        }
-        free(lnw);
-    }
+    for (int32_t i = 0; i < n; ++i)
+        transition_row(tau, dist, eta, n, alpha, beta, gamma, i, P + (size_t)i * (size_t)n);
+}
+
+/* The same for the listed rows only (count rows, P_rows is count x n). */
+ORACLE_API void oracle_transition_rows(const float* tau, const float* dist, const float* eta,
+                                       int32_t n, float alpha, float beta, float gamma,
+                                       const int32_t* rows, int32_t count, float* P_rows) {
+#pragma omp parallel for schedule(static)
+    for (int32_t k = 0; k < count; ++k)
+        transition_row(tau, dist, eta, n, alpha, beta, gamma, rows[k],
+                       P_rows + (size_t)k * (size_t)n);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -486,3 +486,15 @@ def test_pheromone_bounds_along_run(oracle_lib):
         assert off.max() <= upper * (1 + slack)
         assert np.array_equal(tau, tau.T)
         assert np.all(np.diag(tau) == 0)
+
+
+def test_transition_rows_subset(oracle_lib):
+    """The row-subset entry point returns the full transition's rows."""
+    n = 37
+    D = inst.distance_matrix(inst.uniform_cities(n, 12))
+    rng = np.random.default_rng(1)
+    tau = (rng.random((n, n)) + 0.1).astype(np.float32)
+    np.fill_diagonal(tau, 0.0)
+    P = oracle_lib.transition(tau, D, 1.0, 2.0, 1.3)
+    rows = [0, 5, 36, 5]
+    assert np.array_equal(oracle_lib.transition_rows(tau, D, 1.0, 2.0, 1.3, rows), P[rows])
