@@ -108,3 +108,36 @@ def test_product_path_does_not_reach_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), os.path.join(dirpath, f)
+
+
+def test_batch_and_setter_argument_errors_before_any_device_call():
+    from paper_2404_04895_amd import _native
+    L = _native.lib()
+    i32 = lambda *v: (ctypes.c_int32 * len(v))(*v)
+    i64 = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    u64 = lambda *v: (ctypes.c_uint64 * len(v))(*v)
+    # sizes: empty batch, an instance below 3 cities or above the maximum, no ants
+    assert L.aco_batch_workspace_bytes(i32(10), i32(10), 0) == 0
+    assert L.aco_batch_workspace_bytes(i32(10, 2), i32(10, 10), 2) == 0
+    assert L.aco_batch_workspace_bytes(i32(_native.MAX_CITIES + 1), i32(4), 1) == 0
+    assert L.aco_batch_workspace_bytes(i32(10), i32(0), 1) == 0
+    assert L.aco_batch_workspace_bytes(i32(10, 3), i32(10, 1), 2) > 0
+    out = ctypes.c_void_p(123)
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+
+    def create(n, m, count, offsets=None):
+        offsets = offsets or i64(*([0] * max(count, 1)))
+        return L.aco_batch_create(fake, offsets, n, m, u64(*([0] * max(count, 1))), count, 1.0,
+                                  2.0, 0.5, 1.0, None, ws, 1 << 30, None, ctypes.byref(out))
+
+    assert create(i32(10), i32(10), 0) == _native.ACO_EINVAL            # empty batch
+    assert create(i32(10, 2), i32(10, 10), 2) == _native.ACO_EINVAL     # n = 2
+    assert create(i32(10), i32(0), 1) == _native.ACO_EINVAL             # no ants
+    assert create(i32(10), i32(10), 1, i64(-1)) == _native.ACO_EINVAL   # bad offset
+    assert out.value is None
+    # the selection, walk and bounds setters on a NULL context
+    assert L.aco_set_selection(None, 0) == _native.ACO_EINVAL
+    assert L.aco_set_sorted_walk(None, 4) == _native.ACO_EINVAL
+    assert L.aco_set_tau_bounds(None, 0.0, 1.0) == _native.ACO_EINVAL
+    assert L.aco_set_schedule(None, -1) == _native.ACO_EINVAL
