@@ -621,24 +621,27 @@ __device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchP
 }
 
 // Each wave takes tasks (instance, first ant, ant count, schedule) from its
-// home queue (its workgroup index mod kQueues), then from the other queues in
-// turn, until all are empty.  Every wave reaches the exit: each queue is
-// finite, a wave leaves a queue at its first empty read, and each task is
-// bounded by its instance size.
+// home queue (its workgroup index mod kQueues) until that is empty.  Then
+// lanes 0..kQueues-1 read the queue counters at once and the wave moves to
+// the first queue that still looks open, until none does.  A counter only
+// grows, so a stale read can only make a queue look open; the atomic then
+// finds it empty, and the wave probes again.  Every wave reaches the exit:
+// the tasks are finite and each is bounded by its instance size.
 __global__ __launch_bounds__(kWave) void batch_construct_kernel(
     const BatchInstance* __restrict__ insts, const BatchTask* __restrict__ tasks,
     const int32_t* __restrict__ queue_start, uint32_t* __restrict__ queues,
     const IterState* __restrict__ state, BatchPools pools) {
     extern __shared__ uint32_t lds[];
     const uint32_t iter = state->iter;
+    const int32_t lane = static_cast<int32_t>(threadIdx.x);
     const int32_t home = static_cast<int32_t>(blockIdx.x % kQueues);
-    for (int32_t k = 0; k < kQueues; ++k) {
-        const int32_t q = (home + k) % kQueues;
+    int32_t q = home;
+    for (;;) {
         const int32_t begin = queue_start[q];
         const uint32_t size = static_cast<uint32_t>(queue_start[q + 1] - begin);
         for (;;) {
             uint32_t t = 0;
-            if (threadIdx.x == 0) t = atomicAdd(queues + q, 1u);
+            if (lane == 0) t = atomicAdd(queues + q, 1u);
             t = __builtin_amdgcn_readfirstlane(t);
             if (t >= size) break;
             const BatchTask task = tasks[begin + static_cast<int32_t>(t)];
@@ -652,6 +655,16 @@ __global__ __launch_bounds__(kWave) void batch_construct_kernel(
             }
             __syncthreads();
         }
+        bool open = false;
+        if (lane < kQueues) {
+            const int32_t p = (home + lane) % kQueues;
+            const uint32_t taken =
+                __hip_atomic_load(queues + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            open = taken < static_cast<uint32_t>(queue_start[p + 1] - queue_start[p]);
+        }
+        const uint64_t any = __ballot(open);
+        if (any == 0ull) break;
+        q = (home + __builtin_ctzll(any)) % kQueues;
     }
 }
 
