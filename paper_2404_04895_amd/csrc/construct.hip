@@ -51,13 +51,18 @@ __device__ __forceinline__ int32_t score_key(float p, uint32_t word, uint32_t ta
 // All-reduce over the G lanes of a group (every lane gets the result):
 // quad butterflies, rotations by 4 and 8 within each 16-lane row, then the
 // permlane swaps that pair rows (G >= 32) and wave halves (G = 64).
+// The DPP moves take the operation's identity as their old value: every
+// source lane of these patterns lies in the same row, so the identity is only
+// ever seen from a lane that exec has switched off, and it lets the compiler
+// fold each move into the max / min itself (one DPP instruction per stage).
 template <int G, bool IS_MAX>
 __device__ __forceinline__ int32_t group_reduce(int32_t v) {
     auto op = [](int32_t a, int32_t b) { return IS_MAX ? max(a, b) : min(a, b); };
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xF, 0xF, false));  // row_ror:4
-    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    constexpr int32_t id = IS_MAX ? INT32_MIN : INT32_MAX;
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x128, 0xF, 0xF, false));  // row_ror:8
     if constexpr (G >= 32) {
         const auto sw = __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(v),
                                                          static_cast<uint32_t>(v), false, false);
@@ -399,8 +404,10 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                                                static_cast<uint32_t>(s),
                                                static_cast<uint32_t>(ant), I.iter, I.key0,
                                                I.key1);
-            const int32_t q = j & 3;
-            const uint32_t w = q == 0 ? r.w0 : (q == 1 ? r.w1 : (q == 2 ? r.w2 : r.w3));
+            // word j mod 4 of the block's four, picked without a branch
+            const uint32_t w01 = (j & 1) ? r.w1 : r.w0;
+            const uint32_t w23 = (j & 1) ? r.w3 : r.w2;
+            const uint32_t w = (j & 2) ? w23 : w01;
             const int32_t key = score_key(p, w, 0u);
             if (key > best_key || (key == best_key && j < best_j)) {
                 best_key = key;
