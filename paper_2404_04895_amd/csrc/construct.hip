@@ -278,7 +278,7 @@ __device__ __forceinline__ int32_t roulette_select(const InstanceView& I, const 
 
 // Build the tours of up to 64/G ants of one instance: group g of this wave
 // builds ant ant0 + g if g < nants.  `lds` is this wave's LDS region of
-// (64/G) * group_lds_words(n, LIVE) words.
+// (64/G) * group_lds_words(n, LIVE, G) words.
 // ---- per-window output -----------------------------------------------------
 
 // Lane k of the calling lane's group (k the same on every lane of the wave).
@@ -301,14 +301,17 @@ __device__ __forceinline__ int32_t group_lane(int32_t v, int32_t k) {
 // Write out a window of the tour: lane l of the group holds entry base + l
 // (l < cnt); `prev` is the entry before the window (-1 for the first).  Each
 // lane writes its entry and the successor / predecessor maps of the edge
-// that ends at it, and gathers that edge's length; the lengths are then
-// added to `len` one by one in tour order, so the FP64 sum is the
-// sequential one.  Runs once per G steps, which keeps scattered stores and
-// the random distance gathers out of the per-step chain.
+// that ends at it, and gathers that edge's length into the group's LDS
+// window (+0 where there is no edge).  The group's first lane then adds the
+// window to `len` entry by entry in tour order, so the FP64 sum is the
+// sequential one (adding +0 to a sum of non-negative terms changes nothing).
+// Runs once per G steps, which keeps scattered stores and the random
+// distance gathers out of the per-step chain.
 template <int G>
 __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tour, int32_t ant,
                                              int32_t base, int32_t cnt, int32_t win,
-                                             int32_t prev, int32_t gl, double& len) {
+                                             int32_t prev, int32_t gl, double* window,
+                                             double& len) {
     int32_t from = __shfl_up(win, 1, G);
     if (gl == 0) from = prev;
     float d = 0.0f;
@@ -320,8 +323,25 @@ __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tou
             d = I.dist[static_cast<size_t>(from) * I.ld + win];
         }
     }
-    for (int32_t k = (prev < 0) ? 1 : 0; k < cnt; ++k)
-        len += static_cast<double>(__int_as_float(group_lane<G>(__float_as_int(d), k)));
+    window[gl] = static_cast<double>(d);
+    // the group's first lane reads what the other lanes just wrote
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (gl == 0) {
+        double acc = len;
+#pragma unroll
+        for (int32_t k = 0; k < G; k += 2) {
+            const double2 pair = *reinterpret_cast<const double2*>(window + k);
+            acc += pair.x;
+            acc += pair.y;
+        }
+        len = acc;
+    }
+    // the window is written again G steps later; no lane may get there first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // The first batch of one row's sorted entries, loaded one step ahead for
@@ -434,7 +454,9 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     const int32_t ant = ant0 + g;
     const int32_t nblk = (n + 3) >> 2;
     const int32_t nwords = mask_words(nblk);
-    uint32_t* visited = lds + g * group_lds_words(n, LIVE);
+    uint32_t* area = lds + g * group_lds_words(n, LIVE, G);
+    double* lengths_window = reinterpret_cast<double*>(area);
+    uint32_t* visited = area + 2 * G;
     uint16_t* live = reinterpret_cast<uint16_t*>(visited + nwords);
 
     for (int32_t w = gl; w < nwords; w += G) {
@@ -525,7 +547,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         if ((s & (G - 1)) == G - 1 || s == n - 1) {
             const int32_t base = s & ~(G - 1);
             const int32_t cnt = s - base + 1;
-            flush_window<G>(I, tour, ant, base, cnt, win, prev, gl, len);
+            flush_window<G>(I, tour, ant, base, cnt, win, prev, gl, lengths_window, len);
             prev = group_lane<G>(win, cnt - 1);
         }
         cur = next;
@@ -586,7 +608,7 @@ template <int G, bool LIVE>
 hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipStream_t stream) {
     constexpr int32_t kGroups = kWave / G;
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(kGroups) *
-                       static_cast<size_t>(group_lds_words(I.n, LIVE));
+                       static_cast<size_t>(group_lds_words(I.n, LIVE, G));
     const dim3 grid((m + kGroups - 1) / kGroups);
     if (selection == kSelRoulette) {
         hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelRoulette>), grid, dim3(kWave), lds,
@@ -707,7 +729,7 @@ int32_t sorted_default_schedule(int32_t m) {
 
 size_t wave_lds_bytes(int32_t n, int32_t sched) {
     return sizeof(uint32_t) * static_cast<size_t>(kWave / schedule_lanes(sched)) *
-           static_cast<size_t>(group_lds_words(n, schedule_live(sched)));
+           static_cast<size_t>(group_lds_words(n, schedule_live(sched), schedule_lanes(sched)));
 }
 
 bool roulette_fits(int32_t n, int32_t sched) {
