@@ -540,9 +540,19 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         }
         // record the step: visited bit now; tour entry, maps and length per window
         const int32_t word = next >> 5;
-        const uint32_t bits = visited[word] | (1u << (next & 31));
-        __builtin_amdgcn_wave_barrier();
-        if (gl == 0) visited[word] = bits;
+        uint32_t bits = 0u;
+        if constexpr (LIVE) {
+            // the live list needs the block's bits after this step
+            bits = visited[word] | (1u << (next & 31));
+            __builtin_amdgcn_wave_barrier();
+            if (gl == 0) visited[word] = bits;
+        } else {
+            // an LDS OR with no return value: nothing on the step's chain
+            // waits for it, and the wave's later LDS reads see it
+            if (gl == 0)
+                __hip_atomic_fetch_or(visited + word, 1u << (next & 31), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
         if (gl == (s & (G - 1))) win = next;
         if ((s & (G - 1)) == G - 1 || s == n - 1) {
             const int32_t base = s & ~(G - 1);
