@@ -73,13 +73,50 @@ __global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
 }
 
 constexpr int32_t kTopThreads = 256;
+constexpr int32_t kWave = 64;
+
+// Sum of v over this lane and every lane above it in the wavefront.
+__device__ __forceinline__ uint32_t wave_suffix_sum(uint32_t v) {
+    const int32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int32_t off = 1; off < kWave; off <<= 1) {
+        const uint32_t u = __shfl_down(v, off, kWave);
+        if (lane + off < kWave) v += u;
+    }
+    return v;
+}
+
+// Sum of v over this lane and every lane below it in the wavefront.
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t v) {
+    const int32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int32_t off = 1; off < kWave; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off, kWave);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// LDS bytes of topk_rows_kernel before the row itself: histogram, segment
+// counts, scalars, then the K (key, city) slots.
+constexpr size_t topk_lds_bytes(int32_t K) {
+    return sizeof(uint32_t) * (256 + kTopThreads + 4) +
+           static_cast<size_t>(K) * (sizeof(uint32_t) + sizeof(uint16_t));
+}
+// Largest dynamic LDS a top-K launch asks for (the full sort's 16384 slots
+// use as much); rows that would need more are read from global memory.
+constexpr size_t kTopStagedMax = 16384 * (sizeof(uint32_t) + sizeof(uint16_t)) +
+                                 sizeof(uint32_t) * (256 + kTopThreads + 4);
 
 // The first K entries of the full sort of a row, for K < n (K a power of two):
 // every entry whose key exceeds the K-th largest key T, and the entries equal
 // to T with the smallest cities, then sorted.  T is found by a radix select,
 // most significant byte first: four 256-bin LDS histograms over the entries
 // that match the bytes chosen so far.  The entries equal to T are ranked in
-// city order through per-thread contiguous segments and a prefix sum.
+// city order through per-thread contiguous segments and a prefix sum.  With
+// STAGED the row is first copied to LDS (one coalesced pass), and every later
+// pass reads it there.
+template <bool STAGED>
 __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __restrict__ P,
                                                                 int32_t n, int32_t ld,
                                                                 int32_t K,
@@ -87,13 +124,19 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
                                                                 uint16_t* __restrict__ Js) {
     extern __shared__ uint32_t sh[];
     uint32_t* hist = sh;                                          // 256
-    uint32_t* seg_count = sh + 256;                               // kTopThreads
+    uint32_t* seg_count = sh + 256;                               // one per wavefront
     uint32_t* misc = sh + 256 + kTopThreads;                      // 4
     uint32_t* key = sh + 256 + kTopThreads + 4;                   // K
     uint16_t* city = reinterpret_cast<uint16_t*>(key + K);        // K
     const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
-    const uint32_t* bits = reinterpret_cast<const uint32_t*>(P + row);
     const int32_t tid = threadIdx.x;
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(P + row);
+    if constexpr (STAGED) {
+        uint32_t* staged = reinterpret_cast<uint32_t*>(city + K);  // n words
+        for (int32_t i = tid; i < n; i += kTopThreads) staged[i] = bits[i];
+        bits = staged;
+        __syncthreads();
+    }
 
     uint32_t prefix = 0u, mask = 0u;
     uint32_t need = static_cast<uint32_t>(K);
@@ -105,16 +148,25 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
             if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 0xFFu], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            // the digit d holding the need-th largest: count from the top bin down
-            uint32_t above = 0u;
-            int32_t d = 255;
-            for (; d > 0; --d) {
-                if (above + hist[d] >= need) break;
-                above += hist[d];
+        if (tid < kWave) {
+            // the digit d holding the need-th largest, counting from the top
+            // bin down: lane l holds bins 4l .. 4l+3; the last lane whose
+            // bins and all above reach `need` holds d
+            const uint4 h = reinterpret_cast<const uint4*>(hist)[tid];
+            const uint32_t own = h.x + h.y + h.z + h.w;
+            const uint32_t from_here = wave_suffix_sum(own);
+            const uint64_t reach = __ballot(from_here >= need);
+            if (tid == 63 - __builtin_clzll(reach)) {
+                uint32_t above = from_here - own;  // entries in the bins above lane tid's
+                const uint32_t bins[4] = {h.x, h.y, h.z, h.w};
+                int32_t q = 3;
+                for (; q > 0; --q) {
+                    if (above + bins[q] >= need) break;
+                    above += bins[q];
+                }
+                misc[0] = static_cast<uint32_t>(4 * tid + q);
+                misc[1] = above;
             }
-            misc[0] = static_cast<uint32_t>(d);
-            misc[1] = above;
         }
         __syncthreads();
         prefix |= misc[0] << shift;
@@ -129,21 +181,16 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
     const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
     uint32_t eq = 0u;
     for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
-    seg_count[tid] = eq;
+    // exclusive prefix sum of the segment counts in thread order: within each
+    // wavefront, then the totals of the wavefronts before it
+    const uint32_t incl = wave_prefix_sum(eq);
+    if ((tid & (kWave - 1)) == kWave - 1) seg_count[tid / kWave] = incl;
     if (tid == 0) misc[2] = 0u;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0u;
-        for (int32_t t = 0; t < kTopThreads; ++t) {
-            const uint32_t c = seg_count[t];
-            seg_count[t] = run;
-            run += c;
-        }
-    }
-    __syncthreads();
+    uint32_t rank = incl - eq;
+    for (int32_t w = 0; w < tid / kWave; ++w) rank += seg_count[w];
     // entries above T take slots need .. K-1 (their order is fixed by the sort
     // below); the equal ones of rank < need take slots 0 .. need-1
-    uint32_t rank = seg_count[tid];
     for (int32_t i = lo; i < hi; ++i) {
         const uint32_t k = bits[i];
         int32_t slot = -1;
@@ -188,10 +235,15 @@ hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, int32_t walk,
                             uint16_t* Js, hipStream_t stream) {
     const int32_t K = sorted_prefix(n, walk);
     if (K < n) {
-        const size_t lds = sizeof(uint32_t) * (256 + kTopThreads + 4) +
-                           static_cast<size_t>(K) * (sizeof(uint32_t) + sizeof(uint16_t));
-        hipLaunchKernelGGL(topk_rows_kernel, dim3(n), dim3(kTopThreads), lds, stream, P, n, ld,
-                           K, Ps, Js);
+        const size_t lds = topk_lds_bytes(K);
+        const size_t staged = lds + sizeof(uint32_t) * static_cast<size_t>(n);
+        if (staged <= kTopStagedMax) {
+            hipLaunchKernelGGL(topk_rows_kernel<true>, dim3(n), dim3(kTopThreads), staged, stream,
+                               P, n, ld, K, Ps, Js);
+        } else {
+            hipLaunchKernelGGL(topk_rows_kernel<false>, dim3(n), dim3(kTopThreads), lds, stream,
+                               P, n, ld, K, Ps, Js);
+        }
         return hipGetLastError();
     }
     int32_t n2 = 2;
@@ -204,13 +256,15 @@ hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, int32_t walk,
 }
 
 hipError_t prepare_sort_kernel() {
-    // n2 <= 16384: 96 KB of LDS; the top-K kernel needs K < n <= 16384 slots
-    const int bytes = static_cast<int>(16384 * (sizeof(uint32_t) + sizeof(uint16_t)) +
-                                       sizeof(uint32_t) * (256 + kTopThreads + 4));
+    // n2 <= 16384: 96 KB of slots; a top-K launch asks for at most as much
+    const int bytes = static_cast<int>(kTopStagedMax);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sort_rows_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(topk_rows_kernel),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(topk_rows_kernel<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(topk_rows_kernel<false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 

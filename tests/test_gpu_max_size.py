@@ -30,8 +30,12 @@ def test_max_size_n16384():
     col = Colony(torch.from_numpy(D).cuda(), 1.0, 2.0, 0.1, 1.0, m)
     sample = np.array([0, 3])
     seed = 5
+    # walk 8 keeps K = 512 entries per row (top-K from a row staged in LDS),
+    # 128 keeps 8192 (top-K reading the row from global memory), 256 sorts
+    # whole rows
     for selection, gamma, walk in (("adair", 1.5, None), ("adair-sorted", 1.5, 8),
-                                   ("adair-sorted", 1.5, 256), ("roulette", 1.0, None)):
+                                   ("adair-sorted", 1.5, 128), ("adair-sorted", 1.5, 256),
+                                   ("roulette", 1.0, None)):
         col.set_selection(selection)
         if walk is not None:
             col.set_sorted_walk(walk)
@@ -49,6 +53,16 @@ def test_max_size_n16384():
             o_tours, o_len = oracle.construct(P, D, seed, 0, sample)
             assert np.array_equal(tours[sample], o_tours), (selection, walk)
             assert np.array_equal(lengths[sample].view(np.uint32), o_len.view(np.uint32))
+        if walk is not None:
+            # sampled rows' kept prefixes: the first K of (P descending, city ascending)
+            K = min(max(64, 1 << (64 * walk - 1).bit_length()), n)
+            Ps, Js = col.sorted_rows()
+            for c in (0, 8191, n - 1):
+                want = np.lexsort((np.arange(n), -P[c].astype(np.float64)))[:K]
+                got_j = Js[c, :K].cpu().numpy().view(np.uint16).astype(np.int64)
+                assert np.array_equal(got_j, want), (walk, c)
+                assert np.array_equal(Ps[c, :K].cpu().numpy(), P[c, want]), (walk, c)
+            del Ps, Js
         del P
     # the update at full size, from the last construct
     tau_prev = col.tau().cpu().numpy()
