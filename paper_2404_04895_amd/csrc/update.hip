@@ -111,6 +111,10 @@ struct RowArgs {
     float tau_min, tau_max;  // MAX-MIN bounds applied after the update (0, +inf: none)
 };
 
+// Loads are issued kUnroll iterations at a time, before any of them is used,
+// so that a thread waits for memory once per kUnroll iterations.
+constexpr int32_t kUnroll = 4;
+
 template <int T>
 __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
     const int32_t tid = threadIdx.x & (T - 1);
@@ -118,30 +122,74 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
     if (a.apply_deposit) {
         for (int32_t j = tid; j < a.n; j += T) acc[j] = 0ull;
         sync_row<T>();
-        for (int32_t k = tid; k < a.m; k += T) {
-            const int64_t q = a.weight[k];
-            if (q != 0) {
-                atomicAdd(&acc[a.succ[k]], static_cast<unsigned long long>(q));
-                atomicAdd(&acc[a.pred[k]], static_cast<unsigned long long>(q));
+        // every ant below m has a successor and a predecessor of row i, so
+        // they are read whatever the ant's weight
+        for (int32_t k0 = tid; k0 < a.m; k0 += T * kUnroll) {
+            int64_t q[kUnroll];
+            int32_t s[kUnroll], p[kUnroll];
+#pragma unroll
+            for (int32_t u = 0; u < kUnroll; ++u) {
+                const int32_t k = k0 + u * T;
+                q[u] = 0;
+                s[u] = 0;
+                p[u] = 0;
+                if (k < a.m) {
+                    q[u] = a.weight[k];
+                    s[u] = a.succ[k];
+                    p[u] = a.pred[k];
+                }
+            }
+#pragma unroll
+            for (int32_t u = 0; u < kUnroll; ++u) {
+                if (q[u] != 0) {
+                    atomicAdd(&acc[s[u]], static_cast<unsigned long long>(q[u]));
+                    atomicAdd(&acc[p[u]], static_cast<unsigned long long>(q[u]));
+                }
             }
         }
         sync_row<T>();
     }
     double local_max = -INFINITY;
-    for (int32_t j = tid; j < a.n; j += T) {
-        if (j == a.i) continue;
-        float t = a.tau[j];
-        if (a.apply_deposit) {
-            const double add = static_cast<double>(static_cast<int64_t>(acc[j])) * a.unit;
-            t = static_cast<float>(__fma_rn(a.keep, static_cast<double>(t), add));
-            t = fminf(fmaxf(t, a.tau_min), a.tau_max);
-            a.tau[j] = t;
+    for (int32_t j0 = tid; j0 < a.n; j0 += T * kUnroll) {
+        float tv[kUnroll], ev[kUnroll];
+#pragma unroll
+        for (int32_t u = 0; u < kUnroll; ++u) {
+            const int32_t j = j0 + u * T;
+            tv[u] = 0.0f;
+            ev[u] = 1.0f;
+            if (j < a.n) {
+                tv[u] = a.tau[j];
+                ev[u] = a.eta ? a.eta[j] : a.dist[j];
+            }
         }
-        const double ln_eta = a.eta ? log(static_cast<double>(a.eta[j]))
-                                    : -log(static_cast<double>(a.dist[j]));
-        const double w = a.alpha * log(static_cast<double>(t)) + a.beta * ln_eta;
-        lnw[j] = w;
-        local_max = fmax(local_max, w);
+#pragma unroll
+        for (int32_t u = 0; u < kUnroll; ++u) {
+            const int32_t j = j0 + u * T;
+            const bool live = j < a.n && j != a.i;
+            if (a.apply_deposit && live) {
+                const double add = static_cast<double>(static_cast<int64_t>(acc[j])) * a.unit;
+                const float t = static_cast<float>(__fma_rn(a.keep, static_cast<double>(tv[u]), add));
+                tv[u] = fminf(fmaxf(t, a.tau_min), a.tau_max);
+            }
+            if (live) {
+                const double ln_eta = a.eta ? log(static_cast<double>(ev[u]))
+                                            : -log(static_cast<double>(ev[u]));
+                const double w = a.alpha * log(static_cast<double>(tv[u])) + a.beta * ln_eta;
+                lnw[j] = w;
+                local_max = fmax(local_max, w);
+            }
+        }
+        // The stores go last and are not branched per element: a store counts
+        // in the same counter as the loads, and a wait for a load placed after
+        // a conditional store would wait for the store too.  The diagonal
+        // entry is written back unchanged.
+        if (a.apply_deposit) {
+#pragma unroll
+            for (int32_t u = 0; u < kUnroll; ++u) {
+                const int32_t j = j0 + u * T;
+                if (j < a.n) a.tau[j] = tv[u];
+            }
+        }
     }
     const double row_max = row_max_all<T>(local_max, red);
     sync_row<T>();
