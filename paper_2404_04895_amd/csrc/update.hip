@@ -21,7 +21,7 @@ namespace aco {
 
 namespace {
 
-constexpr int kRowThreads = 256;
+constexpr int kRowThreads = 512;
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
