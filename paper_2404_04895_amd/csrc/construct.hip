@@ -279,6 +279,13 @@ __device__ __forceinline__ int32_t roulette_select(const InstanceView& I, const 
 // Build the tours of up to 64/G ants of one instance: group g of this wave
 // builds ant ant0 + g if g < nants.  `lds` is this wave's LDS region of
 // (64/G) * group_lds_words(n, LIVE, G) words.
+// Offset of row c of a matrix with leading dimension ld.  Both are below
+// 2^15 (at most 16384 cities, padded), so a 24-bit multiply, which runs at
+// the full VALU rate, gives the exact product.
+__device__ __forceinline__ size_t row_offset(int32_t c, int32_t ld) {
+    return static_cast<size_t>(__umul24(static_cast<uint32_t>(c), static_cast<uint32_t>(ld)));
+}
+
 // ---- per-window output -----------------------------------------------------
 
 // Lane k of the calling lane's group (k the same on every lane of the wave).
@@ -388,7 +395,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                                                const uint32_t* visited, int32_t gl, int32_t s,
                                                int32_t ant, uint32_t& entries_read,
                                                SortedSpec& spec) {
-    const size_t off = static_cast<size_t>(cur) * I.ld;
+    const size_t off = row_offset(cur, I.ld);
     const float* ps = I.Ps + off;
     const uint16_t* js = I.Js + off;
     int32_t best_key = -1;
@@ -414,7 +421,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
         if (base == 0) {
             spec.city = group_first<G>(__ballot(cand), j);
             if (spec.city >= 0 && gl < limit) {
-                const size_t next = static_cast<size_t>(spec.city) * I.ld + gl;
+                const size_t next = row_offset(spec.city, I.ld) + gl;
                 spec.p = I.Ps[next];
                 spec.j = I.Js[next];
             }
@@ -489,20 +496,21 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         if constexpr (SEL == kSelSorted) {
             if (s > 0) {
                 walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, ant, walk_entries, spec));
-                if (walked < 0) {
-                    ++scanned_steps;
-                    scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
-                }
             }
         }
         if (SEL == kSelRoulette && s > 0) {
-            const float* row = I.P + static_cast<size_t>(cur) * I.ld;
+            const float* row = I.P + row_offset(cur, I.ld);
             next = group_uniform<G>(roulette_select<G, LIVE>(I, row, visited, live,
                                                               LIVE ? nlive : nblk, gl, g, s, ant));
         } else if (walked >= 0) {
             next = walked;
         } else if (s > 0) {
-            const float* row = I.P + static_cast<size_t>(cur) * I.ld;
+            if constexpr (SEL == kSelSorted) {
+                // the walk left this step undecided
+                ++scanned_steps;
+                scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
+            }
+            const float* row = I.P + row_offset(cur, I.ld);
             int32_t best_key = -1;
             int32_t best_j = 0x7FFFFFFF;
             const int32_t span = LIVE ? nlive : nblk;
