@@ -283,7 +283,8 @@ __device__ __forceinline__ int32_t roulette_select(const InstanceView& I, const 
 // 2^15 (at most 16384 cities, padded), so a 24-bit multiply, which runs at
 // the full VALU rate, gives the exact product.
 __device__ __forceinline__ size_t row_offset(int32_t c, int32_t ld) {
-    return static_cast<size_t>(__umul24(static_cast<uint32_t>(c), static_cast<uint32_t>(ld)));
+    const uint32_t e = __umul24(static_cast<uint32_t>(c), static_cast<uint32_t>(ld));
+    return static_cast<size_t>(e);
 }
 
 // ---- per-window output -----------------------------------------------------
@@ -351,6 +352,31 @@ __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tou
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The sorted rows as buffer resources: a load then takes one 32-bit offset in
+// a VGPR (the base and the range sit in SGPRs), and an offset past the range
+// reads zero.  The range is the n x ld matrix.
+constexpr int32_t kBufferWord3 = 0x00020000;  // raw 32-bit loads on gfx9-family chips
+
+struct SortedRows {
+    __amdgpu_buffer_rsrc_t p;  // FP32 values
+    __amdgpu_buffer_rsrc_t j;  // uint16 cities
+};
+
+__device__ __forceinline__ SortedRows sorted_rows(const InstanceView& I) {
+    const int32_t elems = I.n * I.ld;  // at most 2^28
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(I.Ps), 0, 4 * elems, kBufferWord3),
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(I.Js), 0, 2 * elems,
+                                              kBufferWord3)};
+}
+
+__device__ __forceinline__ float sorted_p(const SortedRows& R, uint32_t e) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(R.p, 4 * e, 0, 0));
+}
+
+__device__ __forceinline__ int32_t sorted_j(const SortedRows& R, uint32_t e) {
+    return static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b16(R.j, 2 * e, 0, 0));
+}
+
 // The first batch of one row's sorted entries, loaded one step ahead for
 // the city most likely to be taken next (`city` is -1 when there is none).
 struct SortedSpec {
@@ -395,9 +421,8 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                                                const uint32_t* visited, int32_t gl, int32_t s,
                                                int32_t ant, uint32_t& entries_read,
                                                SortedSpec& spec) {
-    const size_t off = row_offset(cur, I.ld);
-    const float* ps = I.Ps + off;
-    const uint16_t* js = I.Js + off;
+    const SortedRows R = sorted_rows(I);
+    const uint32_t off = __umul24(static_cast<uint32_t>(cur), static_cast<uint32_t>(I.ld));
     int32_t best_key = -1;
     int32_t best_j = 0x7FFFFFFF;
     // 64 * walk is a multiple of G, so a batch is partial only when the limit
@@ -413,17 +438,18 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                 p = spec.p;
                 j = spec.j;
             } else {
-                p = ps[pos];
-                j = js[pos];
+                p = sorted_p(R, off + pos);
+                j = sorted_j(R, off + pos);
             }
         }
         const bool cand = j >= 0 && !((visited[j >> 5] >> (j & 31)) & 1u);
         if (base == 0) {
             spec.city = group_first<G>(__ballot(cand), j);
             if (spec.city >= 0 && gl < limit) {
-                const size_t next = row_offset(spec.city, I.ld) + gl;
-                spec.p = I.Ps[next];
-                spec.j = I.Js[next];
+                const uint32_t next =
+                    __umul24(static_cast<uint32_t>(spec.city), static_cast<uint32_t>(I.ld)) + gl;
+                spec.p = sorted_p(R, next);
+                spec.j = sorted_j(R, next);
             }
         }
         if (cand) {
