@@ -377,6 +377,19 @@ __device__ __forceinline__ int32_t sorted_j(const SortedRows& R, uint32_t e) {
     return static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b16(R.j, 2 * e, 0, 0));
 }
 
+// The transition matrix as a buffer resource (n x ld FP32), and block b of
+// row c through it: one 16-byte load from a 32-bit offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t matrix_rows(const InstanceView& I) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(I.P), 0, 4 * (I.n * I.ld),
+                                             kBufferWord3);
+}
+
+__device__ __forceinline__ float4 matrix_block(__amdgpu_buffer_rsrc_t R, uint32_t row_e,
+                                               int32_t b) {
+    return __builtin_bit_cast(
+        float4, __builtin_amdgcn_raw_buffer_load_b128(R, 4 * (row_e + 4 * static_cast<uint32_t>(b)), 0, 0));
+}
+
 // The first batch of one row's sorted entries, loaded one step ahead for
 // the city most likely to be taken next (`city` is -1 when there is none).
 struct SortedSpec {
@@ -536,7 +549,8 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
                 ++scanned_steps;
                 scanned_blocks += static_cast<uint32_t>(LIVE ? nlive : nblk);
             }
-            const float* row = I.P + row_offset(cur, I.ld);
+            const __amdgpu_buffer_rsrc_t rows = matrix_rows(I);
+            const uint32_t row_e = __umul24(static_cast<uint32_t>(cur), static_cast<uint32_t>(I.ld));
             int32_t best_key = -1;
             int32_t best_j = 0x7FFFFFFF;
             const int32_t span = LIVE ? nlive : nblk;
@@ -544,7 +558,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
                 const int32_t pos = base + gl;
                 if (pos < span) {
                     const int32_t b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
-                    const float4 p = *reinterpret_cast<const float4*>(row + 4 * b);
+                    const float4 p = matrix_block(rows, row_e, b);
                     const PhiloxOut r = philox10_block(static_cast<uint32_t>(b),
                                                        static_cast<uint32_t>(s),
                                                        static_cast<uint32_t>(ant), I.iter,
