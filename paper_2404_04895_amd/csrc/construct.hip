@@ -455,7 +455,10 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                 j = sorted_j(R, off + pos);
             }
         }
-        const bool cand = j >= 0 && !((visited[j >> 5] >> (j & 31)) & 1u);
+        // an empty lane (j = -1) reads word 0 and is then dropped, so the
+        // test needs no branch
+        const int32_t jw = max(j, 0);
+        const bool cand = (j >= 0) & !((visited[jw >> 5] >> (jw & 31)) & 1u);
         if (base == 0) {
             spec.city = group_first<G>(__ballot(cand), j);
             if (spec.city >= 0 && gl < limit) {
