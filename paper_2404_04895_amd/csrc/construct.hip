@@ -287,6 +287,12 @@ __device__ __forceinline__ size_t row_offset(int32_t c, int32_t ld) {
     return static_cast<size_t>(e);
 }
 
+// Chunks of the row a scanning step loads before it scores the first: four
+// where a scan is latency-bound (the sorted walk's rare fallback, the small
+// instances of a batch), one for the full scan of one large instance, which
+// is bound by HBM and slowed by the extra loads in flight.
+constexpr int32_t kScanAhead = 4;
+
 // ---- per-window output -----------------------------------------------------
 
 // Lane k of the calling lane's group (k the same on every lane of the wave).
@@ -492,7 +498,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
     return -1;
 }
 
-template <int G, bool LIVE, int SEL = kSelAdaIR>
+template <int G, bool LIVE, int SEL = kSelAdaIR, int AHEAD = kScanAhead>
 __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nants,
                                 uint32_t* __restrict__ lds) {
     const int32_t lane = threadIdx.x & (kWave - 1);
@@ -557,31 +563,56 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
             int32_t best_key = -1;
             int32_t best_j = 0x7FFFFFFF;
             const int32_t span = LIVE ? nlive : nblk;
-            for (int32_t base = 0; base < span; base += G) {
-                const int32_t pos = base + gl;
-                if (pos < span) {
-                    const int32_t b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
-                    const float4 p = matrix_block(rows, row_e, b);
-                    const PhiloxOut r = philox10_block(static_cast<uint32_t>(b),
-                                                       static_cast<uint32_t>(s),
-                                                       static_cast<uint32_t>(ant), I.iter,
-                                                       I.key0, I.key1);
-                    const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
-                    const int32_t k0 = score_key(p.x, r.w0, taken << 31);
-                    const int32_t k1 = score_key(p.y, r.w1, (taken << 30) & 0x80000000u);
-                    const int32_t k2 = score_key(p.z, r.w2, (taken << 29) & 0x80000000u);
-                    const int32_t k3 = score_key(p.w, r.w3, (taken << 28) & 0x80000000u);
-                    // block winner: strict compares keep the smaller city on ties
-                    const int32_t e01 = (k1 > k0) ? 1 : 0;
-                    const int32_t m01 = max(k0, k1);
-                    const int32_t e23 = (k3 > k2) ? 3 : 2;
-                    const int32_t m23 = max(k2, k3);
-                    const int32_t eb = (m23 > m01) ? e23 : e01;
-                    const int32_t mb = max(m01, m23);
-                    // lane winner: blocks arrive in increasing order
-                    if (mb > best_key) {
-                        best_key = mb;
-                        best_j = 4 * b + eb;
+            // one block of the row: its four scores, the block's winner, then
+            // the lane's (a lane's blocks arrive in increasing order)
+            auto score_block = [&](int32_t b, float4 p) {
+                const PhiloxOut r = philox10_block(static_cast<uint32_t>(b),
+                                                   static_cast<uint32_t>(s),
+                                                   static_cast<uint32_t>(ant), I.iter,
+                                                   I.key0, I.key1);
+                const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
+                const int32_t k0 = score_key(p.x, r.w0, taken << 31);
+                const int32_t k1 = score_key(p.y, r.w1, (taken << 30) & 0x80000000u);
+                const int32_t k2 = score_key(p.z, r.w2, (taken << 29) & 0x80000000u);
+                const int32_t k3 = score_key(p.w, r.w3, (taken << 28) & 0x80000000u);
+                // block winner: strict compares keep the smaller city on ties
+                const int32_t e01 = (k1 > k0) ? 1 : 0;
+                const int32_t m01 = max(k0, k1);
+                const int32_t e23 = (k3 > k2) ? 3 : 2;
+                const int32_t m23 = max(k2, k3);
+                const int32_t eb = (m23 > m01) ? e23 : e01;
+                const int32_t mb = max(m01, m23);
+                if (mb > best_key) {
+                    best_key = mb;
+                    best_j = 4 * b + eb;
+                }
+            };
+            if constexpr (AHEAD == 1) {
+                for (int32_t base = 0; base < span; base += G) {
+                    const int32_t pos = base + gl;
+                    if (pos < span) {
+                        const int32_t b = LIVE ? static_cast<int32_t>(live[pos]) : pos;
+                        score_block(b, matrix_block(rows, row_e, b));
+                    }
+                }
+            } else {
+                // AHEAD chunks of G blocks are loaded before any is scored, so
+                // that a lane waits for memory once per AHEAD chunks
+                for (int32_t base = 0; base < span; base += AHEAD * G) {
+                    float4 pv[AHEAD];
+                    int32_t bv[AHEAD];
+#pragma unroll
+                    for (int32_t u = 0; u < AHEAD; ++u) {
+                        const int32_t pos = base + u * G + gl;
+                        bv[u] = -1;
+                        if (pos < span) {
+                            bv[u] = LIVE ? static_cast<int32_t>(live[pos]) : pos;
+                            pv[u] = matrix_block(rows, row_e, bv[u]);
+                        }
+                    }
+#pragma unroll
+                    for (int32_t u = 0; u < AHEAD; ++u) {
+                        if (bv[u] >= 0) score_block(bv[u], pv[u]);
                     }
                 }
             }
@@ -653,7 +684,8 @@ __global__ __launch_bounds__(kWave) void construct_kernel(InstanceView I, int32_
     extern __shared__ uint32_t lds[];
     constexpr int32_t kGroups = kWave / G;
     const int32_t ant0 = static_cast<int32_t>(blockIdx.x) * kGroups;
-    construct_group<G, LIVE, SEL>(I, ant0, min(kGroups, m - ant0), lds);
+    construct_group<G, LIVE, SEL, SEL == kSelAdaIR ? 1 : kScanAhead>(I, ant0, min(kGroups, m - ant0),
+                                                                     lds);
 }
 
 __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uint32_t ant,
