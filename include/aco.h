@@ -175,12 +175,17 @@ const float* aco_pheromone(const aco_ctx* ctx);
 const float* aco_transition_matrix(const aco_ctx* ctx);
 const int32_t* aco_tours(const aco_ctx* ctx);
 const float* aco_lengths(const aco_ctx* ctx);
-/* The rows of P as last sorted for ACO_SELECT_ADAIR_SORTED, n x ld: values
- * (FP32, descending within a row, ties by ascending city) and their cities
- * (uint16).  Only the first K entries of each row are kept: K = 64 * walk
- * rounded up to a power of two, at most n (the walk never reads further). */
+/* The rows of P as last sorted for ACO_SELECT_ADAIR_SORTED: each row keeps its
+ * first K entries (the walk never reads further), values (FP32, descending,
+ * ties by ascending city) and their cities (uint16), row r at offset r * K of
+ * each device array.  K = aco_sorted_prefix(ctx).  The context owns both
+ * arrays (valid until aco_destroy); NULL for a NULL context. */
 const float* aco_sorted_rows(const aco_ctx* ctx);
 const uint16_t* aco_sorted_cities(const aco_ctx* ctx);
+/* K, the entries each sorted row keeps at the current walk: 64 * walk rounded
+ * up to a power of two, at most n; 0 at a walk of 0 (the walk then reads no
+ * sorted entry and no row is sorted) and for a NULL context. */
+int32_t aco_sorted_prefix(const aco_ctx* ctx);
 
 /* What the ACO_SELECT_ADAIR_SORTED constructs since the previous call (or
  * since aco_create) read, then resets the counts (blocks): out3[0] the sorted

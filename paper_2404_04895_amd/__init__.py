@@ -166,11 +166,13 @@ class Colony:
         return tuple(int(v) for v in out)
 
     def sorted_rows(self):
-        """(values, cities) of the rows of P sorted by the last adair-sorted construct."""
+        """(values, cities) of the rows of P sorted by the last adair-sorted construct:
+        the K entries each row keeps (n x K)."""
         torch = _torch()
-        Ps = self._view(lib().aco_sorted_rows(self._ctx), torch.float32, (self.n, self.ld))
-        Js = self._view(lib().aco_sorted_cities(self._ctx), torch.int16, (self.n, self.ld))
-        return Ps[:, :self.n], Js[:, :self.n]
+        K = int(lib().aco_sorted_prefix(self._ctx))
+        Ps = self._view(lib().aco_sorted_rows(self._ctx), torch.float32, (self.n, K))
+        Js = self._view(lib().aco_sorted_cities(self._ctx), torch.int16, (self.n, K))
+        return Ps, Js
 
     def set_stream(self, stream):
         self._stream = stream

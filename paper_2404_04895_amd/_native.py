@@ -62,6 +62,7 @@ SIGNATURES = {
     "aco_transition_matrix": (_vp, [_vp]),
     "aco_sorted_rows": (_vp, [_vp]),
     "aco_sorted_cities": (_vp, [_vp]),
+    "aco_sorted_prefix": (ctypes.c_int32, [_vp]),
     "aco_sorted_walk_stats": (_i32, [_vp, _vp]),
     "aco_tours": (_vp, [_vp]),
     "aco_lengths": (_vp, [_vp]),

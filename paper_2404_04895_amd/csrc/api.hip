@@ -57,6 +57,12 @@ aco_status bind_device(const aco_ctx* ctx) {
 }
 
 // Sort the rows of the current P for the sorted walk, unless that is done.
+// Entries each sorted row keeps at a walk: none at 0 (the walk then reads no
+// sorted entry and no row is sorted), else the prefix the walk may read.
+int32_t kept_prefix(int32_t n, int32_t walk) {
+    return walk > 0 ? aco::sorted_prefix(n, walk) : 0;
+}
+
 aco_status sort_rows_if_needed(aco_ctx* ctx) {
     if (ctx->selection != ACO_SELECT_ADAIR_SORTED || ctx->rows_sorted) return ACO_OK;
     if (ctx->walk > 0)
@@ -344,7 +350,8 @@ aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches) {
     if (batches < 0 || batches > ACO_SORTED_WALK_MAX)
         return fail(ACO_EINVAL, "aco_set_sorted_walk: %d outside [0, %d]", batches,
                     ACO_SORTED_WALK_MAX);
-    if (batches > ctx->walk) ctx->rows_sorted = false;  // a longer sorted prefix is needed
+    // another prefix length is another layout (rows are K entries apart)
+    if (kept_prefix(ctx->n, batches) != kept_prefix(ctx->n, ctx->walk)) ctx->rows_sorted = false;
     ctx->walk = batches;
     return ACO_OK;
 }
@@ -441,6 +448,7 @@ aco_status aco_sorted_walk_stats(aco_ctx* ctx, uint64_t* out3) {
 
 const float* aco_sorted_rows(const aco_ctx* ctx) { return ctx ? ctx->buf.Ps : nullptr; }
 const uint16_t* aco_sorted_cities(const aco_ctx* ctx) { return ctx ? ctx->buf.Js : nullptr; }
+int32_t aco_sorted_prefix(const aco_ctx* ctx) { return ctx ? kept_prefix(ctx->n, ctx->walk) : 0; }
 const int32_t* aco_tours(const aco_ctx* ctx) { return ctx ? ctx->buf.tours : nullptr; }
 const float* aco_lengths(const aco_ctx* ctx) { return ctx ? ctx->buf.lengths : nullptr; }
 int32_t aco_deposit_scale(const aco_ctx* ctx) { return ctx ? ctx->S : -1; }

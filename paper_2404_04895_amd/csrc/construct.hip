@@ -360,7 +360,8 @@ __device__ __forceinline__ void flush_window(const InstanceView& I, int32_t* tou
 
 // The sorted rows as buffer resources: a load then takes one 32-bit offset in
 // a VGPR (the base and the range sit in SGPRs), and an offset past the range
-// reads zero.  The range is the n x ld matrix.
+// reads zero.  Rows are K entries apart, K the prefix each keeps, so that the
+// first batches of all rows lie close together.
 constexpr int32_t kBufferWord3 = 0x00020000;  // raw 32-bit loads on gfx9-family chips
 
 struct SortedRows {
@@ -369,7 +370,7 @@ struct SortedRows {
 };
 
 __device__ __forceinline__ SortedRows sorted_rows(const InstanceView& I) {
-    const int32_t elems = I.n * I.ld;  // at most 2^28
+    const int32_t elems = I.n * I.sorted_ld;  // at most 2^28
     return {__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(I.Ps), 0, 4 * elems, kBufferWord3),
             __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(I.Js), 0, 2 * elems,
                                               kBufferWord3)};
@@ -441,7 +442,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                                                int32_t ant, uint32_t& entries_read,
                                                SortedSpec& spec) {
     const SortedRows R = sorted_rows(I);
-    const uint32_t off = __umul24(static_cast<uint32_t>(cur), static_cast<uint32_t>(I.ld));
+    const uint32_t off = __umul24(static_cast<uint32_t>(cur), static_cast<uint32_t>(I.sorted_ld));
     int32_t best_key = -1;
     int32_t best_j = 0x7FFFFFFF;
     // 64 * walk is a multiple of G, so a batch is partial only when the limit
@@ -469,7 +470,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
             spec.city = group_first<G>(__ballot(cand), j);
             if (spec.city >= 0 && gl < limit) {
                 const uint32_t next =
-                    __umul24(static_cast<uint32_t>(spec.city), static_cast<uint32_t>(I.ld)) + gl;
+                    __umul24(static_cast<uint32_t>(spec.city), static_cast<uint32_t>(I.sorted_ld)) + gl;
                 spec.p = sorted_p(R, next);
                 spec.j = sorted_j(R, next);
             }
@@ -737,6 +738,7 @@ __device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchP
     I.iter = iter;
     I.Ps = nullptr;
     I.Js = nullptr;
+    I.sorted_ld = 0;
     I.walk = 0;
     I.walk_stats = nullptr;
     construct_group<G, LIVE>(I, ant0, nants, lds);
@@ -860,6 +862,7 @@ hipError_t launch_construct(const Buffers& B, int32_t n, int32_t ld, int32_t m, 
     I.iter = iter;
     I.Ps = B.Ps;
     I.Js = B.Js;
+    I.sorted_ld = sorted_prefix(n, walk);
     I.walk = walk;
     I.walk_stats = B.walk_stats;
     return launch_construct_view(I, m, sched, selection, stream);

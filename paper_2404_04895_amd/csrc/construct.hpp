@@ -20,6 +20,7 @@ struct InstanceView {
     uint32_t key0, key1, iter;
     const float* Ps;     // n x ld rows of P sorted by value (sorted walk only)
     const uint16_t* Js;  // n x ld city of each sorted entry
+    int32_t sorted_ld;   // row stride of Ps / Js: the K entries each row keeps
     int32_t walk;        // sorted batches per step before the scan
     unsigned long long* walk_stats;  // sorted walk: entries read, steps scanned, blocks scanned
 };

@@ -9,7 +9,8 @@
 // the FP32 bit patterns order like the values.  A bitonic network over a
 // power of two puts them in descending order of P, ties by ascending city;
 // empty slots sort last.  The network is data-oblivious, so the order is the
-// same on every run.  Each compare-exchange step reads and writes LDS only,
+// same on every run.  The kept rows are written K entries apart (row r at
+// r * K), so that the hot first entries of all rows share pages.  Each compare-exchange step reads and writes LDS only,
 // with one barrier between steps.
 #include "internal.hpp"
 
@@ -66,9 +67,10 @@ __global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
     }
     __syncthreads();
     bitonic_lds(key, city, n2);
+    const size_t out = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(n);  // K = n
     for (int32_t i = tid; i < n; i += nt) {
-        Ps[row + i] = __uint_as_float(key[i]);
-        Js[row + i] = city[i];
+        Ps[out + i] = __uint_as_float(key[i]);
+        Js[out + i] = city[i];
     }
 }
 
@@ -207,9 +209,10 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
     }
     __syncthreads();
     bitonic_lds(key, city, K);
+    const size_t out = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(K);
     for (int32_t i = tid; i < K; i += kTopThreads) {
-        Ps[row + i] = __uint_as_float(key[i]);
-        Js[row + i] = city[i];
+        Ps[out + i] = __uint_as_float(key[i]);
+        Js[out + i] = city[i];
     }
 }
 

@@ -35,15 +35,16 @@ def _colony(D, alpha, beta, rho, m_max, **kw):
 def _check_sorted_rows(col, P, walk):
     """The kept prefix of every row equals the first K entries of the row
     sorted by (P descending, city ascending), K = 64 * walk rounded up to a
-    power of two, at most n."""
+    power of two, at most n; nothing is kept at a walk of 0."""
     Ps, Js = col.sorted_rows()
-    Ps = Ps.cpu().numpy()
-    Js = Js.cpu().numpy().view(np.uint16).astype(np.int64)
     n = P.shape[0]
     K = 64
     while K < 64 * walk:
         K *= 2
-    K = min(K, n)
+    K = min(K, n) if walk > 0 else 0
+    assert tuple(Ps.shape) == tuple(Js.shape) == (n, K)  # rows are K entries apart
+    Ps = Ps.cpu().numpy()
+    Js = Js.cpu().numpy().view(np.uint16).astype(np.int64)
     for c in range(n):
         want = np.lexsort((np.arange(n), -P[c].astype(np.float64)))[:K]
         assert np.array_equal(Js[c, :K], want), "row %d" % c
@@ -109,7 +110,7 @@ def test_sorted_walk_converged_pheromone():
     col.sync()
     assert np.array_equal(col.tours(m).cpu().numpy(), o_tours)
     assert np.array_equal(col.lengths(m).cpu().numpy().view(np.uint32), o_len.view(np.uint32))
-    _check_sorted_rows(col, P, 4)
+    _check_sorted_rows(col, P, 8)  # the default walk
     col.close()
 
 
