@@ -5,7 +5,7 @@ construction for every ant (with tour lengths and successor/predecessor
 maps), best-so-far, elite weights, index-mapped deposit, evaporation and the
 next transition matrix.  Inputs are resident in HBM before timing starts.
 
-The construct runs the sorted walk by default on instances of 600 cities or
+The construct runs the sorted walk by default on instances of 400 cities or
 more (--selection adair-sorted).  It picks exactly the AdaIR argmax, bit for
 bit, without scoring the cities that provably cannot win.  Its rows are
 sorted in the update that builds P, which costs more than the walk saves on
@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 COUNTERS_FILES = {"adair": os.path.join(ROOT, "profiles", "construct_counters.json"),
                   "adair-sorted": os.path.join(ROOT, "profiles", "construct_sorted_counters.json")}
-SORTED_MIN_N = 600     # measured crossover of the sorted walk against the full scan (m = n)
+SORTED_MIN_N = 400     # the sorted walk loses at 159 cities and wins at 442 (m = n)
 KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/philox.hpp"]
 
 
