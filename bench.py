@@ -155,7 +155,7 @@ def bench_batch(args, w):
     import numpy as np
     import torch
 
-    from paper_2404_04895_amd import Batch, autotune
+    from paper_2404_04895_amd import SCHED_SORTED, Batch, autotune
 
     dists = w.dists()
     ns = np.array([d.shape[0] for d in dists], dtype=np.int64)
@@ -173,12 +173,21 @@ def bench_batch(args, w):
         stream.synchronize()
         elapsed = time.perf_counter() - t0
         lens, _, _ = b.best()
+        sorted_member = np.array([b.view(i).schedule & SCHED_SORTED != 0 for i in range(len(ns))])
+        b.sorted_walk_stats()  # reset the counts
         b.run(args.steps, use_graph=False, time_construct=True)
         construct_ms, launches = b.construct_time()
+        walk = b.sorted_walk_stats()
         b.close()
     stream.synchronize()
     ant_steps = int((ns * (ns - 1)).sum())
-    bytes_launch = int((ns * (ns - 1) * (4 * ns + 8)).sum())
+    # full-scan members read whole rows; sorted-walk members what their walks
+    # counted (as for one instance), plus their tour writes and distance gathers
+    full = ~sorted_member
+    entries, _, blocks = walk
+    bytes_launch = int((ns[full] * (ns[full] - 1) * (4 * ns[full] + 8)).sum()) + int(
+        (entries * 6 + blocks * 16) / launches) + int(
+        (ns[sorted_member] * (ns[sorted_member] - 1) * 8).sum())
     avg_construct_s = construct_ms / launches / 1e3
     achieved = bytes_launch / avg_construct_s / 1e9
     line = {
@@ -204,6 +213,7 @@ def bench_batch(args, w):
                      "avg_launch_ms": avg_construct_s * 1e3},
         "construct_ant_steps_per_s": ant_steps / avg_construct_s,
         "mean_best_len": float(np.mean(lens)),
+        "sorted_walk_members": int(sorted_member.sum()),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_batch(w, dists)

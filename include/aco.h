@@ -294,6 +294,15 @@ typedef struct {
     int32_t schedule;
 } aco_schedule_entry;
 
+/* Batch schedule flag: OR'd into ACO_SCHED_G16, ACO_SCHED_G32 or ACO_SCHED_G64,
+ * the instances of that row construct with AdaIR's sorted walk (as
+ * ACO_SELECT_ADAIR_SORTED at the default walk of 8 batches) instead of the
+ * full scan, and every iteration also sorts their rows of P, whole (Sec. 2.4;
+ * the same tours bit for bit).  Only rows with n_max <= ACO_BATCH_SORTED_MAX_N
+ * may carry it. */
+#define ACO_SCHED_SORTED 16
+#define ACO_BATCH_SORTED_MAX_N 1024
+
 /* Device views of one member of a batch (borrowed; valid until destroy). */
 typedef struct {
     int32_t n, ld, m, deposit_scale, schedule;
@@ -329,7 +338,9 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
 
 /* Install a schedule table (host array, copied) and the number of persistent
  * construct wavefronts (0: 4096).  Instances no row covers use ACO_SCHED_AUTO.
- * Blocks (uploads the task queue).  Errors: ACO_EINVAL for unknown codes. */
+ * Blocks (uploads the task queue).  Errors: ACO_EINVAL for unknown codes, and
+ * for ACO_SCHED_SORTED on a live-list schedule or a row with n_max above
+ * ACO_BATCH_SORTED_MAX_N. */
 aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table,
                                    int32_t entries, int32_t persistent_waves);
 
@@ -360,6 +371,12 @@ aco_status aco_batch_best(aco_batch* b, float* lens_host, int32_t* iters_host,
 
 /* Device views of instance i.  Errors: ACO_EINVAL for i out of range. */
 aco_status aco_batch_instance(const aco_batch* b, int32_t i, aco_batch_view* view);
+
+/* What the sorted walks of the members with ACO_SCHED_SORTED read since the
+ * previous call (or since aco_batch_create), summed over those members, then
+ * resets the counts: out3 as aco_sorted_walk_stats.  Blocks.
+ * Errors: ACO_EINVAL for a NULL pointer. */
+aco_status aco_batch_sorted_walk_stats(aco_batch* b, uint64_t* out3);
 
 /* Block until the batch's enqueued work is done; reports device errors. */
 aco_status aco_batch_sync(aco_batch* b);

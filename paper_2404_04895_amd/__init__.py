@@ -12,13 +12,14 @@ import ctypes
 import numpy as np
 
 from . import _native
-from ._native import (SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64,
-                      SCHED_G64_LIVE, SCHEDULES, AcoError, AcoParams, BatchView, ScheduleEntry,
-                      check, lib)
+from ._native import (BATCH_SORTED_MAX_N, SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE,
+                      SCHED_G64, SCHED_G64_LIVE, SCHED_SORTED, SCHEDULES, SORTED_SCHEDULES,
+                      AcoError, AcoParams, BatchView, ScheduleEntry, check, lib)
 
 __all__ = ["Colony", "Batch", "MlpTrainer", "edge_ranks", "mlp_eta", "mlp_features",
            "mlp_targets", "mlp_round", "MLP_PARAMS", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
-           "leading_dim", "MAX_CITIES", "SCHEDULES", "SCHED_AUTO"]
+           "leading_dim", "MAX_CITIES", "SCHEDULES", "SCHED_AUTO", "SCHED_SORTED",
+           "SORTED_SCHEDULES", "BATCH_SORTED_MAX_N"]
 
 MAX_CITIES = _native.MAX_CITIES
 MLP_PARAMS = _native.MLP_PARAMS
@@ -330,6 +331,14 @@ class Batch:
 
     def sync(self):
         check(lib().aco_batch_sync(self._b), "aco_batch_sync")
+
+    def sorted_walk_stats(self):
+        """(entries read, steps scanned, blocks scanned) of the sorted walks of the
+        members with SCHED_SORTED since the previous call; resets the counts."""
+        out = np.zeros(3, np.uint64)
+        check(lib().aco_batch_sorted_walk_stats(self._b, out.ctypes.data_as(ctypes.c_void_p)),
+              "aco_batch_sorted_walk_stats")
+        return tuple(int(v) for v in out)
 
     def best(self):
         lens = np.zeros(self.count, np.float32)

@@ -35,6 +35,10 @@ class BatchView(ctypes.Structure):
 
 SCHED_AUTO, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE = -1, 0, 1, 2, 3, 4
 SCHEDULES = (SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE)
+# batch only: OR'd into a lane schedule without a live list, the sorted walk
+SCHED_SORTED = 16
+BATCH_SORTED_MAX_N = 1024
+SORTED_SCHEDULES = tuple(s | SCHED_SORTED for s in (SCHED_G16, SCHED_G32, SCHED_G64))
 BATCH_GRAPH, BATCH_TIME_CONSTRUCT = 1, 2
 SELECT_ADAIR, SELECT_ROULETTE, SELECT_ADAIR_SORTED = 0, 1, 2
 
@@ -64,6 +68,7 @@ SIGNATURES = {
     "aco_sorted_cities": (_vp, [_vp]),
     "aco_sorted_prefix": (ctypes.c_int32, [_vp]),
     "aco_sorted_walk_stats": (_i32, [_vp, _vp]),
+    "aco_batch_sorted_walk_stats": (_i32, [_vp, _vp]),
     "aco_tours": (_vp, [_vp]),
     "aco_lengths": (_vp, [_vp]),
     "aco_deposit_scale": (_i32, [_vp]),

@@ -94,7 +94,7 @@ def refine(workload="batched-512-uniform-n50-500", out_path=DEFAULT_TABLE, start
     more than `gain` (relative).  Then the persistent-wave count is chosen."""
     import aco_instances as inst
 
-    from . import SCHEDULES
+    from . import BATCH_SORTED_MAX_N, SCHEDULES, SORTED_SCHEDULES
     w = inst.BATCH_WORKLOADS[workload]
     dists = w.dists()
     table, waves = start if start is not None else load_table()
@@ -116,7 +116,9 @@ def refine(workload="batched-512-uniform-n50-500", out_path=DEFAULT_TABLE, start
     for sweep in range(sweeps):
         changed = False
         for i in used:
-            for sched in SCHEDULES:
+            # the sorted walk is a candidate wherever the batch allows it
+            candidates = SCHEDULES + (SORTED_SCHEDULES if table[i][0] <= BATCH_SORTED_MAX_N else ())
+            for sched in candidates:
                 if sched == table[i][1]:
                     continue
                 trial = [list(e) for e in table]

@@ -27,8 +27,8 @@ int32_t batch_ld(int32_t n) { return (n + 31) / 32 * 32; }  // 128-byte rows
 
 struct BatchLayout {
     size_t insts, tasks, queue_start, rows, queue, state, gammas, dist, tau, P, tours, lengths, succ, pred,
-        weight, best_tour, best, row_min, lower, flags, total;
-    int64_t mat_elems, tour_elems, succ_elems, ant_elems, city_elems;
+        weight, best_tour, best, row_min, lower, flags, sorted_p, sorted_j, walk_stats, total;
+    int64_t mat_elems, tour_elems, succ_elems, ant_elems, city_elems, sorted_elems;
     int32_t max_task_count, nrows;
 };
 
@@ -43,6 +43,8 @@ BatchLayout make_batch_layout(const int32_t* n, const int32_t* m, int32_t count)
         L.city_elems += n[i];
         L.max_task_count += m[i];
         L.nrows += n[i];
+        // room for whole sorted rows, for members the sorted walk may serve
+        if (n[i] <= ACO_BATCH_SORTED_MAX_N) L.sorted_elems += static_cast<int64_t>(n[i]) * n[i];
     }
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -70,6 +72,9 @@ BatchLayout make_batch_layout(const int32_t* n, const int32_t* m, int32_t count)
     L.row_min = take(sizeof(float) * ACO_MAX_CITIES);
     L.lower = take(sizeof(double) * count);
     L.flags = take(sizeof(uint32_t) * 4);
+    L.sorted_p = take(sizeof(float) * L.sorted_elems);
+    L.sorted_j = take(sizeof(uint16_t) * L.sorted_elems);
+    L.walk_stats = take(sizeof(unsigned long long) * 3);
     L.total = off;
     return L;
 }
@@ -91,6 +96,7 @@ struct aco_batch {
     int32_t waves = kDefaultWaves;
     int32_t ntasks = 0;
     size_t task_lds = 0;
+    bool any_sorted = false;  // some member constructs with the sorted walk
     int32_t max_ld = 0;
     uint32_t iter = 0;
     std::vector<float> gammas;  // host copy of the last run's schedule (kept alive for the copy)
@@ -115,6 +121,15 @@ int32_t pick_schedule(const aco_batch* b, int32_t n) {
     return aco::default_schedule(n);
 }
 
+bool schedule_ok(const aco_schedule_entry& e) {
+    if (e.schedule == ACO_SCHED_AUTO) return true;
+    const int32_t base = e.schedule & ~ACO_SCHED_SORTED;
+    if (!aco::schedule_valid(base)) return false;
+    if (e.schedule & ACO_SCHED_SORTED)
+        return !aco::schedule_live(base) && e.n_max <= ACO_BATCH_SORTED_MAX_N;
+    return true;
+}
+
 // Rebuild the construct task queues for the current schedule table and
 // upload them.  Instances go, largest first, to the queue with the least work
 // so far (work = ant-steps times row length, m (n - 1) n); within a queue the
@@ -123,16 +138,20 @@ aco_status upload_tasks(aco_batch* b) {
     std::vector<std::vector<aco::BatchTask>> per(aco::kQueues);
     std::vector<double> load(aco::kQueues, 0.0);
     size_t lds = 0;
+    b->any_sorted = false;
     for (int32_t i : b->order) {
-        const aco::BatchInstance& in = b->insts[i];
+        aco::BatchInstance& in = b->insts[i];
         const int32_t sched = pick_schedule(b, in.n);
-        const int32_t per_wave = 64 / aco::schedule_lanes(sched);
+        const int32_t base = sched & ~ACO_SCHED_SORTED;
+        in.sorted = (sched & ACO_SCHED_SORTED) ? 1 : 0;
+        b->any_sorted = b->any_sorted || in.sorted;
+        const int32_t per_wave = 64 / aco::schedule_lanes(base);
         const int32_t q = static_cast<int32_t>(
             std::min_element(load.begin(), load.end()) - load.begin());
         for (int32_t a = 0; a < in.m; a += per_wave)
             per[q].push_back(aco::BatchTask{i, a, std::min(per_wave, in.m - a), sched});
         load[q] += static_cast<double>(in.m) * (in.n - 1) * in.n;
-        lds = std::max(lds, aco::wave_lds_bytes(in.n, sched));
+        lds = std::max(lds, aco::wave_lds_bytes(in.n, base));
     }
     std::vector<aco::BatchTask> tasks;
     std::vector<int32_t> start(aco::kQueues + 1, 0);
@@ -149,6 +168,9 @@ aco_status upload_tasks(aco_batch* b) {
     ACO_HIP(hipMemcpyAsync(b->dev.queue_start, start.data(), sizeof(int32_t) * start.size(),
                            hipMemcpyHostToDevice, b->stream),
             "upload queue starts");
+    ACO_HIP(hipMemcpyAsync(b->dev.insts, b->insts.data(), sizeof(aco::BatchInstance) * b->count,
+                           hipMemcpyHostToDevice, b->stream),
+            "upload descriptors");
     ACO_HIP(hipStreamSynchronize(b->stream), "upload tasks (sync)");
     b->ntasks = static_cast<int32_t>(tasks.size());
     b->task_lds = lds;
@@ -166,6 +188,8 @@ aco_status enqueue_iteration(aco_batch* b, hipEvent_t before = nullptr,
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, &b->dev.state->gamma_next,
                                    true, b->alpha, b->beta, b->rho, b->stream),
             "batch rows");
+    if (b->any_sorted)
+        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->layout.nrows, b->stream), "batch sort rows");
     ACO_HIP(aco::launch_batch_advance(b->dev, b->stream), "batch advance");
     return ACO_OK;
 }
@@ -272,6 +296,9 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
     b->dev.pools.weight = reinterpret_cast<int64_t*>(w + L.weight);
     b->dev.pools.best_tour = reinterpret_cast<int32_t*>(w + L.best_tour);
     b->dev.pools.best = reinterpret_cast<aco::BestRecord*>(w + L.best);
+    b->dev.pools.sorted_p = reinterpret_cast<float*>(w + L.sorted_p);
+    b->dev.pools.sorted_j = reinterpret_cast<uint16_t*>(w + L.sorted_j);
+    b->dev.pools.walk_stats = reinterpret_cast<unsigned long long*>(w + L.walk_stats);
     float* row_min = reinterpret_cast<float*>(w + L.row_min);
     double* lower = reinterpret_cast<double*>(w + L.lower);
     uint32_t* flags = reinterpret_cast<uint32_t*>(w + L.flags);
@@ -298,7 +325,7 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
 
     // descriptors, largest instance first for the queues
     b->insts.resize(count);
-    int64_t om = 0, ot = 0, os = 0, oa = 0, oc = 0;
+    int64_t om = 0, ot = 0, os = 0, oa = 0, oc = 0, osr = 0;
     for (int32_t i = 0; i < count; ++i) {
         aco::BatchInstance& in = b->insts[i];
         in.n = n_host[i];
@@ -310,10 +337,12 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
         in.off_succ = os;
         in.off_ants = oa;
         in.off_cities = oc;
+        in.off_sorted = osr;
         in.key0 = static_cast<uint32_t>(seeds_host[i]);
         in.key1 = static_cast<uint32_t>(seeds_host[i] >> 32);
         in.S = aco::quantisation_exponent(lb[i], m_host[i], Q);
-        in.pad = 0.0f;
+        in.sorted = 0;
+        if (in.n <= ACO_BATCH_SORTED_MAX_N) osr += static_cast<int64_t>(in.n) * in.n;
         om += static_cast<int64_t>(in.n) * in.ld;
         ot += static_cast<int64_t>(in.m) * in.n;
         os += static_cast<int64_t>(in.n) * in.m;
@@ -343,6 +372,7 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
                                       b->dev.pools.P + in.off_mat, b->stream);
     }
     if (e == hipSuccess) e = aco::launch_clear_best(b->dev.pools.best, count, b->stream);
+    if (e == hipSuccess) e = aco::launch_clear_counters(b->dev.pools.walk_stats, 3, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bail(aco::hip_fail(e, "batch init"));
     if (aco_status st = upload_tasks(b)) return bail(st);
@@ -356,9 +386,9 @@ aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table
     if (entries < 0 || (entries > 0 && !table))
         return fail(ACO_EINVAL, "aco_batch_set_schedules: bad table");
     for (int32_t k = 0; k < entries; ++k)
-        if (table[k].schedule != ACO_SCHED_AUTO && !aco::schedule_valid(table[k].schedule))
-            return fail(ACO_EINVAL, "aco_batch_set_schedules: unknown schedule %d",
-                        table[k].schedule);
+        if (!schedule_ok(table[k]))
+            return fail(ACO_EINVAL, "aco_batch_set_schedules: schedule %d not allowed for n_max %d",
+                        table[k].schedule, table[k].n_max);
     if (persistent_waves < 0) return fail(ACO_EINVAL, "aco_batch_set_schedules: waves < 0");
     b->table.assign(table, table + entries);
     std::stable_sort(b->table.begin(), b->table.end(),
@@ -390,6 +420,8 @@ aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t flags) {
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, b->dev.gammas, false,
                                    b->alpha, b->beta, b->rho, b->stream),
             "batch transition");
+    if (b->any_sorted)
+        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->layout.nrows, b->stream), "batch sort rows");
     const bool timed = (flags & ACO_BATCH_TIME_CONSTRUCT) != 0;
     const bool graph = !timed && (flags & ACO_BATCH_GRAPH) && b->stream != nullptr;
     if (graph && (b->graph_stale || !b->graph_exec)) {
@@ -464,6 +496,18 @@ aco_status aco_batch_construct_time(aco_batch* b, double* ms_total, int32_t* lau
     }
     if (ms_total) *ms_total = total;
     if (launches) *launches = b->timed_launches;
+    return ACO_OK;
+}
+
+aco_status aco_batch_sorted_walk_stats(aco_batch* b, uint64_t* out3) {
+    if (!b) return fail(ACO_EINVAL, "null batch");
+    if (!out3) return fail(ACO_EINVAL, "aco_batch_sorted_walk_stats: out is NULL");
+    unsigned long long v[3] = {0, 0, 0};
+    ACO_HIP(hipMemcpyAsync(v, b->dev.pools.walk_stats, sizeof(v), hipMemcpyDeviceToHost, b->stream),
+            "batch walk stats");
+    ACO_HIP(hipStreamSynchronize(b->stream), "batch walk stats (sync)");
+    for (int k = 0; k < 3; ++k) out3[k] = static_cast<uint64_t>(v[k]);
+    ACO_HIP(aco::launch_clear_counters(b->dev.pools.walk_stats, 3, b->stream), "walk stats reset");
     return ACO_OK;
 }
 

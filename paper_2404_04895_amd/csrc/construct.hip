@@ -719,7 +719,7 @@ hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipSt
 
 // ---- persistent construct over a batch of instances -----------------------
 
-template <int G, bool LIVE>
+template <int G, bool LIVE, bool SORTED = false>
 __device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchPools& pools,
                                          uint32_t iter, int32_t ant0, int32_t nants,
                                          uint32_t* lds) {
@@ -736,12 +736,22 @@ __device__ __forceinline__ void run_task(const BatchInstance& inst, const BatchP
     I.key0 = inst.key0;
     I.key1 = inst.key1;
     I.iter = iter;
-    I.Ps = nullptr;
-    I.Js = nullptr;
-    I.sorted_ld = 0;
-    I.walk = 0;
     I.walk_stats = nullptr;
-    construct_group<G, LIVE>(I, ant0, nants, lds);
+    if constexpr (SORTED) {
+        // whole rows, sorted by the update that built this P
+        I.Ps = pools.sorted_p + inst.off_sorted;
+        I.Js = pools.sorted_j + inst.off_sorted;
+        I.sorted_ld = inst.n;
+        I.walk = kBatchWalk;
+        I.walk_stats = pools.walk_stats;
+        construct_group<G, false, kSelSorted>(I, ant0, nants, lds);
+    } else {
+        I.Ps = nullptr;
+        I.Js = nullptr;
+        I.sorted_ld = 0;
+        I.walk = 0;
+        construct_group<G, LIVE>(I, ant0, nants, lds);
+    }
 }
 
 // Each wave takes tasks (instance, first ant, ant count, schedule) from its
@@ -775,6 +785,15 @@ __global__ __launch_bounds__(kWave) void batch_construct_kernel(
                 case kSched32: run_task<32, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
                 case kSched32Live: run_task<32, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
                 case kSched64: run_task<64, false>(inst, pools, iter, task.ant0, task.nants, lds); break;
+                case kSched16 | kSchedSorted:
+                    run_task<16, false, true>(inst, pools, iter, task.ant0, task.nants, lds);
+                    break;
+                case kSched32 | kSchedSorted:
+                    run_task<32, false, true>(inst, pools, iter, task.ant0, task.nants, lds);
+                    break;
+                case kSched64 | kSchedSorted:
+                    run_task<64, false, true>(inst, pools, iter, task.ant0, task.nants, lds);
+                    break;
                 default: run_task<64, true>(inst, pools, iter, task.ant0, task.nants, lds); break;
             }
             __syncthreads();

@@ -36,6 +36,7 @@ enum : int32_t {
     kSched32Live = 2,  // 32 lanes per ant, live-block list
     kSched64 = 3,      // one ant per wave
     kSched64Live = 4,  // one ant per wave, live-block list
+    kSchedSorted = ACO_SCHED_SORTED,  // batch only: OR'd into 16, 32, 64 for the sorted walk
 };
 
 __host__ __device__ constexpr int32_t mask_words(int32_t nblk) { return (nblk + 7) >> 3; }
@@ -67,9 +68,10 @@ struct BatchInstance {
     int64_t off_succ;    // into the succ / pred pools (n x m)
     int64_t off_ants;    // into the lengths / weights pools (m)
     int64_t off_cities;  // into the best-tour pool (n)
+    int64_t off_sorted;  // into the sorted-row pools (n x n), if `sorted`
     uint32_t key0, key1;
     int32_t S;           // deposit quantisation exponent
-    float pad;
+    int32_t sorted;      // 1: constructs with the sorted walk; its rows are sorted each iteration
 };
 
 struct BatchTask {
@@ -100,7 +102,14 @@ struct BatchPools {
     int64_t* weight;
     int32_t* best_tour;
     BestRecord* best;
+    float* sorted_p;     // rows of P sorted by value, whole (instances with `sorted`)
+    uint16_t* sorted_j;  // their cities
+    unsigned long long* walk_stats;  // 3 counters of the sorted walks, as a single instance's
 };
+
+// Sorted batches a batch member's walk reads before it scans (the default of
+// a single instance).
+constexpr int32_t kBatchWalk = 8;
 
 // Construct task queues of the batched engine: one per XCD.  Persistent
 // wave w drains queue w mod kQueues first (workgroups are dispatched to the
@@ -123,6 +132,9 @@ hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched
                                  int32_t selection, hipStream_t stream);
 hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
                                   int32_t grid, hipStream_t stream);
+// Sort the rows of P of every batch member marked `sorted` (one workgroup per
+// row task; members with n <= ACO_BATCH_SORTED_MAX_N).
+hipError_t launch_batch_sort_rows(const BatchDevice& BD, int32_t nrows, hipStream_t stream);
 hipError_t launch_batch_rows(const BatchDevice& BD, int32_t nrows, int32_t max_ld,
                              const float* gamma_ptr, bool apply_deposit, float alpha, float beta,
                              float rho, hipStream_t stream);

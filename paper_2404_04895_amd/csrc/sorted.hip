@@ -12,7 +12,7 @@
 // same on every run.  The kept rows are written K entries apart (row r at
 // r * K), so that the hot first entries of all rows share pages.  Each compare-exchange step reads and writes LDS only,
 // with one barrier between steps.
-#include "internal.hpp"
+#include "construct.hpp"
 
 namespace aco {
 
@@ -216,12 +216,47 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
     }
 }
 
+// Whole rows of the batch members that construct with the sorted walk: one
+// workgroup per row task, the row (n <= ACO_BATCH_SORTED_MAX_N) sorted by a
+// bitonic network in LDS and written n entries apart into the sorted pools.
+// Rows of other members return at once.
+__global__ __launch_bounds__(256) void batch_sort_rows_kernel(const BatchInstance* __restrict__ insts,
+                                                              const RowTask* __restrict__ rows,
+                                                              BatchPools pools) {
+    __shared__ uint32_t key[ACO_BATCH_SORTED_MAX_N];
+    __shared__ uint16_t city[ACO_BATCH_SORTED_MAX_N];
+    const RowTask task = rows[blockIdx.x];
+    const BatchInstance in = insts[task.instance];
+    if (!in.sorted) return;  // the whole workgroup leaves together
+    const int32_t n = in.n;
+    int32_t n2 = 2;
+    while (n2 < n) n2 <<= 1;
+    const float* P = pools.P + in.off_mat + static_cast<int64_t>(task.row) * in.ld;
+    for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
+        key[i] = i < n ? __float_as_uint(P[i]) : 0u;
+        city[i] = static_cast<uint16_t>(i < n ? i : 0xFFFF);
+    }
+    __syncthreads();
+    bitonic_lds(key, city, n2);
+    const int64_t out = in.off_sorted + static_cast<int64_t>(task.row) * n;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        pools.sorted_p[out + i] = __uint_as_float(key[i]);
+        pools.sorted_j[out + i] = city[i];
+    }
+}
+
 __global__ void clear_counters_kernel(unsigned long long* __restrict__ c, int32_t count) {
     const int32_t i = threadIdx.x;
     if (i < count) c[i] = 0ull;
 }
 
 }  // namespace
+
+hipError_t launch_batch_sort_rows(const BatchDevice& BD, int32_t nrows, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_sort_rows_kernel, dim3(nrows), dim3(256), 0, stream, BD.insts, BD.rows,
+                       BD.pools);
+    return hipGetLastError();
+}
 
 hipError_t launch_clear_counters(unsigned long long* c, int32_t count, hipStream_t stream) {
     hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, stream, c, count);

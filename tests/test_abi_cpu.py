@@ -87,6 +87,7 @@ def test_argument_errors_before_any_device_call():
     assert L.aco_run(None, 1, 0, 1, None, None) == _native.ACO_EINVAL
     assert L.aco_deposit_scale(None) == -1
     assert L.aco_sorted_prefix(None) == 0
+    assert L.aco_batch_sorted_walk_stats(None, None) == _native.ACO_EINVAL
     assert L.aco_sorted_rows(None) is None and L.aco_sorted_cities(None) is None
     assert L.aco_uniforms(0, 0, 0, 0, -1, None, None) == _native.ACO_EINVAL
     L.aco_destroy(None)

@@ -82,17 +82,26 @@ def test_batch_equals_independent_runs(use_graph):
 
 
 def test_batch_schedule_tables_do_not_change_results():
+    """Every table gives the same results bit for bit, the sorted walk's
+    (ACO_SCHED_SORTED: rows sorted in each update) included, with graph replay
+    and with direct launches."""
     torch = _torch()
-    from paper_2404_04895_amd import Batch, SCHED_G16, SCHED_G32_LIVE, SCHED_G64, SCHED_G64_LIVE
+    from paper_2404_04895_amd import (Batch, SCHED_G16, SCHED_G32, SCHED_G32_LIVE, SCHED_G64,
+                                      SCHED_G64_LIVE, SCHED_SORTED)
     ns, ms, seeds, dists = _batch_instances()
     stream = torch.cuda.Stream()
     outs = []
     with torch.cuda.stream(stream):
-        for table, waves in [([], 0), ([(64, SCHED_G64), (10**6, SCHED_G64_LIVE)], 97),
-                             ([(400, SCHED_G32_LIVE)], 1), ([(10**6, SCHED_G16)], 4096)]:
+        for table, waves, graph in [
+                ([], 0, True), ([(64, SCHED_G64), (10**6, SCHED_G64_LIVE)], 97, True),
+                ([(400, SCHED_G32_LIVE)], 1, True), ([(10**6, SCHED_G16)], 4096, True),
+                ([(1024, SCHED_G32 | SCHED_SORTED)], 0, True),
+                ([(64, SCHED_G16 | SCHED_SORTED), (128, SCHED_G64),
+                  (400, SCHED_G64 | SCHED_SORTED)], 200, False),
+                ([(100, SCHED_G16), (1024, SCHED_G16 | SCHED_SORTED)], 4096, True)]:
             b = Batch(dists, 1.0, 3.0, 0.1, 1.0, ants=ms, seeds=seeds, stream=stream)
             b.set_schedules(table, waves)
-            b.run(5, use_graph=True)
+            b.run(5, use_graph=graph)
             lens, its, tours = b.best()
             taus = [b.tau(i).cpu().numpy().copy() for i in range(len(ns))]
             outs.append((lens, its, tours, taus))
@@ -102,6 +111,43 @@ def test_batch_schedule_tables_do_not_change_results():
         for i in range(len(ns)):
             assert np.array_equal(tours[i], outs[0][2][i])
             assert np.array_equal(taus[i], outs[0][3][i])
+
+
+def test_batch_sorted_flag_rejected_where_not_allowed():
+    torch = _torch()
+    from paper_2404_04895_amd import (AcoError, Batch, BATCH_SORTED_MAX_N, SCHED_G32_LIVE,
+                                      SCHED_G64, SCHED_SORTED)
+    ns, ms, seeds, dists = _batch_instances()
+    b = Batch(dists[:4], 1.0, 2.0, 0.2, 1.0, ants=ms[:4], seeds=seeds[:4])
+    for table in ([(64, SCHED_G32_LIVE | SCHED_SORTED)],
+                  [(BATCH_SORTED_MAX_N + 1, SCHED_G64 | SCHED_SORTED)],
+                  [(64, 5 | SCHED_SORTED)]):
+        with pytest.raises(AcoError):
+            b.set_schedules(table, 0)
+    b.set_schedules([(BATCH_SORTED_MAX_N, SCHED_G64 | SCHED_SORTED)], 0)
+    assert b.view(3).schedule == SCHED_G64 | SCHED_SORTED
+    b.close()
+
+
+def test_batch_sorted_walk_counts():
+    """The members on the sorted walk report what their walks read: whole
+    batches of their group width, at least one per step, reset by the read."""
+    torch = _torch()
+    from paper_2404_04895_amd import Batch, SCHED_G16, SCHED_G64, SCHED_SORTED
+    ns, ms, seeds, dists = _batch_instances()
+    b = Batch(dists, 1.0, 2.0, 0.2, 1.0, ants=ms, seeds=seeds)
+    b.set_schedules([(100, SCHED_G16), (1024, SCHED_G64 | SCHED_SORTED)], 0)
+    iters = 3
+    b.run(iters, use_graph=False)
+    entries, scanned, blocks = b.sorted_walk_stats()
+    steps = sum(m * (n - 1) for n, m in zip(ns, ms) if n > 100) * iters
+    assert entries % 64 == 0 and entries >= steps * 64
+    assert 0 <= scanned <= steps and blocks >= scanned
+    assert b.sorted_walk_stats() == (0, 0, 0)
+    b.set_schedules([(10**6, SCHED_G16)], 0)
+    b.run(1, use_graph=False)
+    assert b.sorted_walk_stats() == (0, 0, 0)  # no member on the walk
+    b.close()
 
 
 def test_batch_consecutive_runs_continue_the_counter():
