@@ -26,7 +26,7 @@ size_t align256(size_t x) { return aco::align_up(x, 256); }
 int32_t batch_ld(int32_t n) { return (n + 31) / 32 * 32; }  // 128-byte rows
 
 struct BatchLayout {
-    size_t insts, tasks, queue_start, rows, queue, state, gammas, dist, tau, P, tours, lengths, succ, pred,
+    size_t insts, tasks, queue_start, rows, sort_rows, queue, state, gammas, dist, tau, P, tours, lengths, succ, pred,
         weight, best_tour, best, row_min, lower, flags, sorted_p, sorted_j, walk_stats, total;
     int64_t mat_elems, tour_elems, succ_elems, ant_elems, city_elems, sorted_elems;
     int32_t max_task_count, nrows;
@@ -56,6 +56,7 @@ BatchLayout make_batch_layout(const int32_t* n, const int32_t* m, int32_t count)
     L.tasks = take(sizeof(aco::BatchTask) * L.max_task_count);
     L.queue_start = take(sizeof(int32_t) * (aco::kQueues + 1));
     L.rows = take(sizeof(aco::RowTask) * L.nrows);
+    L.sort_rows = take(sizeof(aco::RowTask) * L.nrows);
     L.queue = take(sizeof(uint32_t) * aco::kQueues);
     L.state = take(sizeof(aco::IterState));
     L.gammas = take(sizeof(float) * (kMaxRunIters + 1));
@@ -96,7 +97,7 @@ struct aco_batch {
     int32_t waves = kDefaultWaves;
     int32_t ntasks = 0;
     size_t task_lds = 0;
-    bool any_sorted = false;  // some member constructs with the sorted walk
+    int32_t sort_rows = 0;    // rows of the members on the sorted walk, sorted each iteration
     int32_t max_ld = 0;
     uint32_t iter = 0;
     std::vector<float> gammas;  // host copy of the last run's schedule (kept alive for the copy)
@@ -138,13 +139,14 @@ aco_status upload_tasks(aco_batch* b) {
     std::vector<std::vector<aco::BatchTask>> per(aco::kQueues);
     std::vector<double> load(aco::kQueues, 0.0);
     size_t lds = 0;
-    b->any_sorted = false;
+    std::vector<aco::RowTask> sort_rows;
     for (int32_t i : b->order) {
         aco::BatchInstance& in = b->insts[i];
         const int32_t sched = pick_schedule(b, in.n);
         const int32_t base = sched & ~ACO_SCHED_SORTED;
         in.sorted = (sched & ACO_SCHED_SORTED) ? 1 : 0;
-        b->any_sorted = b->any_sorted || in.sorted;
+        if (in.sorted)
+            for (int32_t r = 0; r < in.n; ++r) sort_rows.push_back(aco::RowTask{i, r});
         const int32_t per_wave = 64 / aco::schedule_lanes(base);
         const int32_t q = static_cast<int32_t>(
             std::min_element(load.begin(), load.end()) - load.begin());
@@ -171,8 +173,14 @@ aco_status upload_tasks(aco_batch* b) {
     ACO_HIP(hipMemcpyAsync(b->dev.insts, b->insts.data(), sizeof(aco::BatchInstance) * b->count,
                            hipMemcpyHostToDevice, b->stream),
             "upload descriptors");
+    if (!sort_rows.empty())
+        ACO_HIP(hipMemcpyAsync(b->dev.sort_rows, sort_rows.data(),
+                               sizeof(aco::RowTask) * sort_rows.size(), hipMemcpyHostToDevice,
+                               b->stream),
+                "upload sort rows");
     ACO_HIP(hipStreamSynchronize(b->stream), "upload tasks (sync)");
     b->ntasks = static_cast<int32_t>(tasks.size());
+    b->sort_rows = static_cast<int32_t>(sort_rows.size());
     b->task_lds = lds;
     b->graph_stale = true;
     return ACO_OK;
@@ -188,8 +196,8 @@ aco_status enqueue_iteration(aco_batch* b, hipEvent_t before = nullptr,
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, &b->dev.state->gamma_next,
                                    true, b->alpha, b->beta, b->rho, b->stream),
             "batch rows");
-    if (b->any_sorted)
-        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->layout.nrows, b->stream), "batch sort rows");
+    if (b->sort_rows > 0)
+        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->sort_rows, b->stream), "batch sort rows");
     ACO_HIP(aco::launch_batch_advance(b->dev, b->stream), "batch advance");
     return ACO_OK;
 }
@@ -283,6 +291,7 @@ aco_status aco_batch_create(const float* dists_dev, const int64_t* dist_offsets_
     b->dev.tasks = reinterpret_cast<aco::BatchTask*>(w + L.tasks);
     b->dev.queue_start = reinterpret_cast<int32_t*>(w + L.queue_start);
     b->dev.rows = reinterpret_cast<aco::RowTask*>(w + L.rows);
+    b->dev.sort_rows = reinterpret_cast<aco::RowTask*>(w + L.sort_rows);
     b->dev.queue = reinterpret_cast<uint32_t*>(w + L.queue);
     b->dev.state = reinterpret_cast<aco::IterState*>(w + L.state);
     b->dev.gammas = reinterpret_cast<float*>(w + L.gammas);
@@ -420,8 +429,8 @@ aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t flags) {
     ACO_HIP(aco::launch_batch_rows(b->dev, b->layout.nrows, b->max_ld, b->dev.gammas, false,
                                    b->alpha, b->beta, b->rho, b->stream),
             "batch transition");
-    if (b->any_sorted)
-        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->layout.nrows, b->stream), "batch sort rows");
+    if (b->sort_rows > 0)
+        ACO_HIP(aco::launch_batch_sort_rows(b->dev, b->sort_rows, b->stream), "batch sort rows");
     const bool timed = (flags & ACO_BATCH_TIME_CONSTRUCT) != 0;
     const bool graph = !timed && (flags & ACO_BATCH_GRAPH) && b->stream != nullptr;
     if (graph && (b->graph_stale || !b->graph_exec)) {

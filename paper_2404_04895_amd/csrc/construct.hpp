@@ -122,6 +122,7 @@ struct BatchDevice {
     BatchTask* tasks;        // queue by queue
     int32_t* queue_start;    // kQueues + 1: first task of each queue, then the total
     RowTask* rows;
+    RowTask* sort_rows;      // the rows of the members on the sorted walk
     uint32_t* queue;         // kQueues counters
     IterState* state;
     float* gammas;  // T + 1 entries
@@ -132,8 +133,8 @@ hipError_t launch_construct_view(const InstanceView& I, int32_t m, int32_t sched
                                  int32_t selection, hipStream_t stream);
 hipError_t launch_batch_construct(const BatchDevice& BD, int32_t ntasks, size_t lds_bytes,
                                   int32_t grid, hipStream_t stream);
-// Sort the rows of P of every batch member marked `sorted` (one workgroup per
-// row task; members with n <= ACO_BATCH_SORTED_MAX_N).
+// Sort the rows of P of the batch members marked `sorted` (the first `nrows`
+// entries of BD.sort_rows; members with n <= ACO_BATCH_SORTED_MAX_N).
 hipError_t launch_batch_sort_rows(const BatchDevice& BD, int32_t nrows, hipStream_t stream);
 hipError_t launch_batch_rows(const BatchDevice& BD, int32_t nrows, int32_t max_ld,
                              const float* gamma_ptr, bool apply_deposit, float alpha, float beta,

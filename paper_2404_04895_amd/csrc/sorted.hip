@@ -216,34 +216,108 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
     }
 }
 
-// Whole rows of the batch members that construct with the sorted walk: one
-// workgroup per row task, the row (n <= ACO_BATCH_SORTED_MAX_N) sorted by a
-// bitonic network in LDS and written n entries apart into the sorted pools.
-// Rows of other members return at once.
-__global__ __launch_bounds__(256) void batch_sort_rows_kernel(const BatchInstance* __restrict__ insts,
-                                                              const RowTask* __restrict__ rows,
-                                                              BatchPools pools) {
-    __shared__ uint32_t key[ACO_BATCH_SORTED_MAX_N];
-    __shared__ uint16_t city[ACO_BATCH_SORTED_MAX_N];
-    const RowTask task = rows[blockIdx.x];
-    const BatchInstance in = insts[task.instance];
-    if (!in.sorted) return;  // the whole workgroup leaves together
-    const int32_t n = in.n;
-    int32_t n2 = 2;
-    while (n2 < n) n2 <<= 1;
-    const float* P = pools.P + in.off_mat + static_cast<int64_t>(task.row) * in.ld;
-    for (int32_t i = threadIdx.x; i < n2; i += blockDim.x) {
-        key[i] = i < n ? __float_as_uint(P[i]) : 0u;
-        city[i] = static_cast<uint16_t>(i < n ? i : 0xFFFF);
-    }
-    __syncthreads();
-    bitonic_lds(key, city, n2);
-    const int64_t out = in.off_sorted + static_cast<int64_t>(task.row) * n;
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        pools.sorted_p[out + i] = __uint_as_float(key[i]);
-        pools.sorted_j[out + i] = city[i];
+// Bitonic network over N = 64 * REGS entries held in registers: entry e sits
+// in register e / 64 of lane e mod 64.  Partners at a stride of 64 or more are
+// in the same lane; nearer ones are exchanged across lanes.  The compare and
+// the order are those of bitonic_lds (value descending, city ascending), so
+// the result is the same.
+template <int REGS>
+__device__ __forceinline__ void bitonic_wave(uint32_t (&k)[REGS], uint32_t (&c)[REGS]) {
+    const int32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int32_t size = 2; size <= 64 * REGS; size <<= 1) {
+#pragma unroll
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64) {
+                const int32_t rs = stride >> 6;
+#pragma unroll
+                for (int32_t r = 0; r < REGS; ++r) {
+                    if (r & rs) continue;  // r holds the lower entry of the pair (r, r | rs)
+                    const int32_t r2 = r | rs;
+                    const bool down = ((r * 64 + lane) & size) == 0;
+                    const bool swap = down ? before(k[r2], c[r2], k[r], c[r])
+                                           : before(k[r], c[r], k[r2], c[r2]);
+                    if (swap) {
+                        const uint32_t tk = k[r], tc = c[r];
+                        k[r] = k[r2];
+                        c[r] = c[r2];
+                        k[r2] = tk;
+                        c[r2] = tc;
+                    }
+                }
+            } else {
+                const bool lower = (lane & stride) == 0;
+#pragma unroll
+                for (int32_t r = 0; r < REGS; ++r) {
+                    const uint32_t kp = static_cast<uint32_t>(__shfl_xor(static_cast<int>(k[r]), stride));
+                    const uint32_t cp = static_cast<uint32_t>(__shfl_xor(static_cast<int>(c[r]), stride));
+                    const bool down = ((r * 64 + lane) & size) == 0;
+                    const uint32_t ka = lower ? k[r] : kp, ca = lower ? c[r] : cp;
+                    const uint32_t kb = lower ? kp : k[r], cb = lower ? cp : c[r];
+                    const bool swap = down ? before(kb, cb, ka, ca) : before(ka, ca, kb, cb);
+                    if (swap) {
+                        k[r] = kp;
+                        c[r] = cp;
+                    }
+                }
+            }
+        }
     }
 }
+
+// One whole row (n <= 64 * REGS) sorted in one wavefront and written n
+// entries apart; slots past n sort last and are not written.
+template <int REGS>
+__device__ __forceinline__ void sort_row_wave(const float* __restrict__ P, int32_t n,
+                                              float* __restrict__ out_p,
+                                              uint16_t* __restrict__ out_j) {
+    const int32_t lane = threadIdx.x & 63;
+    uint32_t k[REGS], c[REGS];
+#pragma unroll
+    for (int32_t r = 0; r < REGS; ++r) {
+        const int32_t e = r * 64 + lane;
+        k[r] = e < n ? __float_as_uint(P[e]) : 0u;
+        c[r] = e < n ? static_cast<uint32_t>(e) : 0xFFFFu;
+    }
+    bitonic_wave<REGS>(k, c);
+#pragma unroll
+    for (int32_t r = 0; r < REGS; ++r) {
+        const int32_t e = r * 64 + lane;
+        if (e < n) {
+            out_p[e] = __uint_as_float(k[r]);
+            out_j[e] = static_cast<uint16_t>(c[r]);
+        }
+    }
+}
+
+// Whole rows of the batch members that construct with the sorted walk: one
+// wavefront per row of the task list (those members' rows only; n <=
+// ACO_BATCH_SORTED_MAX_N), written n entries apart into the sorted pools.
+__global__ __launch_bounds__(64) void batch_sort_rows_kernel(const BatchInstance* __restrict__ insts,
+                                                             const RowTask* __restrict__ rows,
+                                                             BatchPools pools) {
+    const RowTask task = rows[blockIdx.x];
+    const BatchInstance in = insts[task.instance];
+    if (!in.sorted) return;
+    const int32_t n = in.n;
+    const float* P = pools.P + in.off_mat + static_cast<int64_t>(task.row) * in.ld;
+    const int64_t out = in.off_sorted + static_cast<int64_t>(task.row) * n;
+    float* op = pools.sorted_p + out;
+    uint16_t* oj = pools.sorted_j + out;
+    if (n <= 64) {
+        sort_row_wave<1>(P, n, op, oj);
+    } else if (n <= 128) {
+        sort_row_wave<2>(P, n, op, oj);
+    } else if (n <= 256) {
+        sort_row_wave<4>(P, n, op, oj);
+    } else if (n <= 512) {
+        sort_row_wave<8>(P, n, op, oj);
+    } else {
+        sort_row_wave<16>(P, n, op, oj);  // n <= ACO_BATCH_SORTED_MAX_N = 1024
+    }
+}
+
+static_assert(ACO_BATCH_SORTED_MAX_N <= 16 * 64, "the batch row sort holds at most 16 entries per lane");
 
 __global__ void clear_counters_kernel(unsigned long long* __restrict__ c, int32_t count) {
     const int32_t i = threadIdx.x;
@@ -253,8 +327,9 @@ __global__ void clear_counters_kernel(unsigned long long* __restrict__ c, int32_
 }  // namespace
 
 hipError_t launch_batch_sort_rows(const BatchDevice& BD, int32_t nrows, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_sort_rows_kernel, dim3(nrows), dim3(256), 0, stream, BD.insts, BD.rows,
-                       BD.pools);
+    if (nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_sort_rows_kernel, dim3(nrows), dim3(64), 0, stream, BD.insts,
+                       BD.sort_rows, BD.pools);
     return hipGetLastError();
 }
 
