@@ -217,12 +217,13 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
 }
 
 // Bitonic network over N = 64 * REGS entries held in registers: entry e sits
-// in register e / 64 of lane e mod 64.  Partners at a stride of 64 or more are
-// in the same lane; nearer ones are exchanged across lanes.  The compare and
-// the order are those of bitonic_lds (value descending, city ascending), so
-// the result is the same.
+// in register e / 64 of lane e mod 64.  An entry is one 64-bit key, the
+// value's bits above (0xFFFF - city), so that the larger key is the one that
+// comes first (value descending, then city ascending, as in bitonic_lds) and
+// an empty slot (key 0) comes last.  Partners at a stride of 64 or more are in
+// the same lane; nearer ones are exchanged across lanes.
 template <int REGS>
-__device__ __forceinline__ void bitonic_wave(uint32_t (&k)[REGS], uint32_t (&c)[REGS]) {
+__device__ __forceinline__ void bitonic_wave(uint64_t (&v)[REGS]) {
     const int32_t lane = threadIdx.x & 63;
 #pragma unroll
     for (int32_t size = 2; size <= 64 * REGS; size <<= 1) {
@@ -235,30 +236,19 @@ __device__ __forceinline__ void bitonic_wave(uint32_t (&k)[REGS], uint32_t (&c)[
                     if (r & rs) continue;  // r holds the lower entry of the pair (r, r | rs)
                     const int32_t r2 = r | rs;
                     const bool down = ((r * 64 + lane) & size) == 0;
-                    const bool swap = down ? before(k[r2], c[r2], k[r], c[r])
-                                           : before(k[r], c[r], k[r2], c[r2]);
-                    if (swap) {
-                        const uint32_t tk = k[r], tc = c[r];
-                        k[r] = k[r2];
-                        c[r] = c[r2];
-                        k[r2] = tk;
-                        c[r2] = tc;
-                    }
+                    const uint64_t hi = max(v[r], v[r2]), lo = min(v[r], v[r2]);
+                    v[r] = down ? hi : lo;
+                    v[r2] = down ? lo : hi;
                 }
             } else {
                 const bool lower = (lane & stride) == 0;
 #pragma unroll
                 for (int32_t r = 0; r < REGS; ++r) {
-                    const uint32_t kp = static_cast<uint32_t>(__shfl_xor(static_cast<int>(k[r]), stride));
-                    const uint32_t cp = static_cast<uint32_t>(__shfl_xor(static_cast<int>(c[r]), stride));
+                    const uint64_t p = static_cast<uint64_t>(
+                        __shfl_xor(static_cast<unsigned long long>(v[r]), stride));
                     const bool down = ((r * 64 + lane) & size) == 0;
-                    const uint32_t ka = lower ? k[r] : kp, ca = lower ? c[r] : cp;
-                    const uint32_t kb = lower ? kp : k[r], cb = lower ? cp : c[r];
-                    const bool swap = down ? before(kb, cb, ka, ca) : before(ka, ca, kb, cb);
-                    if (swap) {
-                        k[r] = kp;
-                        c[r] = cp;
-                    }
+                    // the lower entry of a descending pair keeps the larger key
+                    v[r] = (lower == down) ? max(v[r], p) : min(v[r], p);
                 }
             }
         }
@@ -272,20 +262,21 @@ __device__ __forceinline__ void sort_row_wave(const float* __restrict__ P, int32
                                               float* __restrict__ out_p,
                                               uint16_t* __restrict__ out_j) {
     const int32_t lane = threadIdx.x & 63;
-    uint32_t k[REGS], c[REGS];
+    uint64_t v[REGS];
 #pragma unroll
     for (int32_t r = 0; r < REGS; ++r) {
         const int32_t e = r * 64 + lane;
-        k[r] = e < n ? __float_as_uint(P[e]) : 0u;
-        c[r] = e < n ? static_cast<uint32_t>(e) : 0xFFFFu;
+        v[r] = e < n ? (static_cast<uint64_t>(__float_as_uint(P[e])) << 32) |
+                           static_cast<uint64_t>(0xFFFFu - static_cast<uint32_t>(e))
+                     : 0ull;
     }
-    bitonic_wave<REGS>(k, c);
+    bitonic_wave<REGS>(v);
 #pragma unroll
     for (int32_t r = 0; r < REGS; ++r) {
         const int32_t e = r * 64 + lane;
         if (e < n) {
-            out_p[e] = __uint_as_float(k[r]);
-            out_j[e] = static_cast<uint16_t>(c[r]);
+            out_p[e] = __uint_as_float(static_cast<uint32_t>(v[r] >> 32));
+            out_j[e] = static_cast<uint16_t>(0xFFFFu - static_cast<uint32_t>(v[r] & 0xFFFFu));
         }
     }
 }
