@@ -247,8 +247,11 @@ __device__ __forceinline__ void bitonic_wave(uint64_t (&v)[REGS]) {
                     const uint64_t p = static_cast<uint64_t>(
                         __shfl_xor(static_cast<unsigned long long>(v[r]), stride));
                     const bool down = ((r * 64 + lane) & size) == 0;
-                    // the lower entry of a descending pair keeps the larger key
-                    v[r] = (lower == down) ? max(v[r], p) : min(v[r], p);
+                    // the lower entry of a descending pair keeps the larger key:
+                    // take the partner's if it is on the wanted side (when the
+                    // keys are equal, either is the same)
+                    const bool keeps_larger = lower == down;
+                    if ((p > v[r]) == keeps_larger) v[r] = p;
                 }
             }
         }
