@@ -129,6 +129,30 @@ def test_batch_sorted_flag_rejected_where_not_allowed():
     b.close()
 
 
+def test_batch_sorted_walk_large_members():
+    """Members of 513 to 1024 cities on the sorted walk (their rows are sorted
+    with 16 entries per lane): the same results as the full scan, bit for bit."""
+    torch = _torch()
+    from paper_2404_04895_amd import (BATCH_SORTED_MAX_N, Batch, SCHED_G32, SCHED_G64_LIVE,
+                                      SCHED_SORTED)
+    ns = [700, BATCH_SORTED_MAX_N, 90]
+    ms = [24, 16, 20]
+    seeds = [11, 12, 13]
+    dists = [inst.distance_matrix(inst.uniform_cities(n, 900 + k)) for k, n in enumerate(ns)]
+    outs = []
+    for table in ([(10**6, SCHED_G64_LIVE)], [(BATCH_SORTED_MAX_N, SCHED_G32 | SCHED_SORTED)]):
+        b = Batch(dists, 1.0, 2.0, 0.2, 1.0, ants=ms, seeds=seeds)
+        b.set_schedules(table, 0)
+        b.run(3, use_graph=False)
+        lens, its, tours = b.best()
+        outs.append((lens, its, tours, [b.tau(i).cpu().numpy().copy() for i in range(3)]))
+        b.close()
+    (l0, i0, t0, tau0), (l1, i1, t1, tau1) = outs
+    assert np.array_equal(l0, l1) and np.array_equal(i0, i1)
+    for i in range(3):
+        assert np.array_equal(t0[i], t1[i]) and np.array_equal(tau0[i], tau1[i]), i
+
+
 def test_batch_sorted_walk_counts():
     """The members on the sorted walk report what their walks read: whole
     batches of their group width, at least one per step, reset by the read."""
