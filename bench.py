@@ -82,28 +82,30 @@ def counter_traffic(n, m, selection="adair"):
     return c.get("bytes_per_launch")
 
 
-def cpu_baseline(w, D, P, budget_s=25.0):
+def cpu_baseline(w, D, P, budget_s=15.0):
     """The oracle as it is, on this host: construct for a sample of ants from
     one P, plus one full update (deposit, evaporation, transition), scaled to
-    ant-steps per second of a whole iteration."""
+    ant-steps per second of a whole iteration.  The sample grows by four ants
+    per thread at a time until about budget_s seconds of construction."""
     import numpy as np
 
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     oracle.construct(P, D, 1, 0, np.arange(threads))   # first call: thread start-up
-    t0 = time.perf_counter()
-    oracle.construct(P, D, 1, 0, np.arange(threads))
-    probe = time.perf_counter() - t0                 # one ant per thread
-    per_round = max(probe, 1e-3)
-    # in bulk a round takes about 0.6 of the lone probe round, so the sample
-    # runs for about 0.6 budget_s
-    rounds = max(1, int(budget_s / per_round))
-    count = min(w.m, rounds * threads)
-    ants = np.arange(count)
-    t0 = time.perf_counter()
-    tours, lengths = oracle.construct(P, D, 1, 0, ants)
-    t_construct = time.perf_counter() - t0
+    chunk = 4 * threads
+    parts_t, parts_l = [], []
+    count, t_construct = 0, 0.0
+    while count < w.m and t_construct < budget_s:
+        ants = np.arange(count, min(w.m, count + chunk))
+        t0 = time.perf_counter()
+        tc, lc = oracle.construct(P, D, 1, 0, ants)
+        t_construct += time.perf_counter() - t0
+        parts_t.append(tc)
+        parts_l.append(lc)
+        count += len(ants)
+    tours = np.concatenate(parts_t)
+    lengths = np.concatenate(parts_l)
     # a full update on tours of the sample (the update's cost does not depend on which ants)
     reps = int(np.ceil(w.m / count))
     all_tours = np.tile(tours, (reps, 1))[:w.m]
