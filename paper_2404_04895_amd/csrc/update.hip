@@ -12,6 +12,12 @@
 //      LDS row (each thread overwrites only its own columns);
 //   4. P_ij = exp((ln W_ij - ln sum_k W_ik) / gamma), the row sum taken after
 //      shifting by the row maximum.
+// When alpha and beta are small non-negative integers (alpha + beta <= 6, the
+// common settings) steps 3-4 take the power form instead: W_ij itself by
+// multiplication (and one division by d^beta), no shift, and P_ij = W_ij / S_i
+// at gamma = 1 or exp((ln W_ij - ln S_i) / gamma) otherwise.  No FP32 input can
+// then leave the FP64 normal range (|log10 W| <= 6 * 44.9 < 307), and both
+// forms give P to FP64 accuracy before its one rounding to FP32.
 // HBM traffic per element: tau read+write, dist (or eta) read, P write.
 #include <math.h>
 
@@ -115,6 +121,13 @@ struct RowArgs {
 // so that a thread waits for memory once per kUnroll iterations.
 constexpr int32_t kUnroll = 4;
 
+// x^k for a small non-negative integer k (wave-uniform), by multiplication.
+__device__ __forceinline__ double int_power(double x, int32_t k) {
+    double r = 1.0;
+    for (int32_t e = 0; e < k; ++e) r *= x;
+    return r;
+}
+
 template <int T>
 __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
     const int32_t tid = threadIdx.x & (T - 1);
@@ -149,6 +162,10 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
         }
         sync_row<T>();
     }
+    // power form: integer exponents with alpha + beta <= 6 (see the header)
+    const bool power = a.alpha >= 0.0 && a.beta >= 0.0 && a.alpha + a.beta <= 6.0 &&
+                       a.alpha == floor(a.alpha) && a.beta == floor(a.beta);
+    const int32_t ia = static_cast<int32_t>(a.alpha), ib = static_cast<int32_t>(a.beta);
     double local_max = -INFINITY;
     for (int32_t j0 = tid; j0 < a.n; j0 += T * kUnroll) {
         float tv[kUnroll], ev[kUnroll];
@@ -172,11 +189,18 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
                 tv[u] = fminf(fmaxf(t, a.tau_min), a.tau_max);
             }
             if (live) {
-                const double ln_eta = a.eta ? log(static_cast<double>(ev[u]))
-                                            : -log(static_cast<double>(ev[u]));
-                const double w = a.alpha * log(static_cast<double>(tv[u])) + a.beta * ln_eta;
-                lnw[j] = w;
-                local_max = fmax(local_max, w);
+                if (power) {
+                    // W = tau^alpha * eta^beta, eta = 1/d unless given
+                    const double t = int_power(static_cast<double>(tv[u]), ia);
+                    const double e = int_power(static_cast<double>(ev[u]), ib);
+                    lnw[j] = a.eta ? t * e : t / e;
+                } else {
+                    const double ln_eta = a.eta ? log(static_cast<double>(ev[u]))
+                                                : -log(static_cast<double>(ev[u]));
+                    const double w = a.alpha * log(static_cast<double>(tv[u])) + a.beta * ln_eta;
+                    lnw[j] = w;
+                    local_max = fmax(local_max, w);
+                }
             }
         }
         // The stores go last and are not branched per element: a store counts
@@ -190,6 +214,31 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
                 if (j < a.n) a.tau[j] = tv[u];
             }
         }
+    }
+    if (power) {
+        sync_row<T>();
+        // lnw holds W itself here
+        const double total =
+            row_sum_fixed<T>(a.n, [&](int32_t j) { return j == a.i ? 0.0 : lnw[j]; }, red);
+        if (a.gamma == 1.0) {
+            // 0 * inf = NaN for an all-zero row, as the log form gives
+            const double inv = 1.0 / total;
+            for (int32_t j = tid; j < a.ld; j += T) {
+                float p = 0.0f;
+                if (j < a.n && j != a.i) p = static_cast<float>(lnw[j] * inv);
+                a.P[j] = p;
+            }
+        } else {
+            const double ln_total = log(total);
+            const double inv_gamma = 1.0 / a.gamma;
+            for (int32_t j = tid; j < a.ld; j += T) {
+                float p = 0.0f;
+                if (j < a.n && j != a.i)
+                    p = static_cast<float>(exp((log(lnw[j]) - ln_total) * inv_gamma));
+                a.P[j] = p;
+            }
+        }
+        return;
     }
     const double row_max = row_max_all<T>(local_max, red);
     sync_row<T>();
