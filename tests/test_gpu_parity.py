@@ -71,6 +71,36 @@ def test_transition_matches_oracle(n):
     col.close()
 
 
+@pytest.mark.parametrize("alpha,beta", [(1.0, 3.0), (0.0, 6.0), (2.0, 4.0), (6.0, 0.0),
+                                        (1.0, 6.0), (1.5, 2.5), (0.5, 1.0)])
+def test_transition_forms_match_oracle(alpha, beta):
+    """The row update forms W by multiplication when alpha and beta are
+    integers with alpha + beta <= 6 and through logarithms otherwise (the
+    first four cases, then three of the other); both must give the oracle's P
+    on pheromone spread over twelve decades, with an FP32 extreme (the largest
+    finite value, the smallest normal or a subnormal) planted in every row."""
+    torch = _torch()
+    n = 131
+    D = inst.distance_matrix(inst.uniform_cities(n, 7))
+    col = _colony(D, alpha, beta, 0.3, 1.0, 4)
+    rng = np.random.default_rng(11)
+    tau = np.zeros((n, col.ld), np.float32)
+    tau[:, :n] = (10.0 ** rng.uniform(-6.0, 6.0, (n, n))).astype(np.float32)
+    for k, v in enumerate((np.finfo(np.float32).max, FLT_MIN, np.float32(1e-44))):
+        rows = np.arange(k, n, 3)
+        tau[rows, (rows + 1 + 17 * k) % n] = v
+    tau[np.arange(n), np.arange(n)] = 0.0
+    col.set_state(torch.from_numpy(tau), 0)
+    for gamma in (1.0, 1.5, 0.7, 4.0):
+        col.transition(gamma)
+        col.sync()
+        P = col.P_padded().cpu().numpy()
+        assert np.all(P[:, n:] == 0.0) and np.all(np.diag(P[:, :n]) == 0.0)
+        ref = oracle.transition(tau[:, :n].copy(), D, alpha, beta, gamma)
+        assert_P_close(P[:, :n], ref, "alpha=%g beta=%g gamma=%g" % (alpha, beta, gamma))
+    col.close()
+
+
 @pytest.mark.parametrize("n,m", [(3, 1), (4, 7), (5, 5), (31, 9), (50, 50), (64, 64), (67, 40),
                                  (256, 33), (257, 64), (1000, 24)])
 def test_construct_bit_exact(n, m):
