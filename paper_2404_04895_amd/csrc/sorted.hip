@@ -99,123 +99,6 @@ __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t v) {
     return v;
 }
 
-// LDS bytes of topk_rows_kernel before the row itself: histogram, segment
-// counts, scalars, then the K (key, city) slots.
-constexpr size_t topk_lds_bytes(int32_t K) {
-    return sizeof(uint32_t) * (256 + kTopThreads + 4) +
-           static_cast<size_t>(K) * (sizeof(uint32_t) + sizeof(uint16_t));
-}
-// Largest dynamic LDS a top-K launch asks for (the full sort's 16384 slots
-// use as much); rows that would need more are read from global memory.
-constexpr size_t kTopStagedMax = 16384 * (sizeof(uint32_t) + sizeof(uint16_t)) +
-                                 sizeof(uint32_t) * (256 + kTopThreads + 4);
-
-// The first K entries of the full sort of a row, for K < n (K a power of two):
-// every entry whose key exceeds the K-th largest key T, and the entries equal
-// to T with the smallest cities, then sorted.  T is found by a radix select,
-// most significant byte first: four 256-bin LDS histograms over the entries
-// that match the bytes chosen so far.  The entries equal to T are ranked in
-// city order through per-thread contiguous segments and a prefix sum.  With
-// STAGED the row is first copied to LDS (one coalesced pass), and every later
-// pass reads it there.
-template <bool STAGED>
-__global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __restrict__ P,
-                                                                int32_t n, int32_t ld,
-                                                                int32_t K,
-                                                                float* __restrict__ Ps,
-                                                                uint16_t* __restrict__ Js) {
-    extern __shared__ uint32_t sh[];
-    uint32_t* hist = sh;                                          // 256
-    uint32_t* seg_count = sh + 256;                               // one per wavefront
-    uint32_t* misc = sh + 256 + kTopThreads;                      // 4
-    uint32_t* key = sh + 256 + kTopThreads + 4;                   // K
-    uint16_t* city = reinterpret_cast<uint16_t*>(key + K);        // K
-    const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
-    const int32_t tid = threadIdx.x;
-    const uint32_t* bits = reinterpret_cast<const uint32_t*>(P + row);
-    if constexpr (STAGED) {
-        uint32_t* staged = reinterpret_cast<uint32_t*>(city + K);  // n words
-        for (int32_t i = tid; i < n; i += kTopThreads) staged[i] = bits[i];
-        bits = staged;
-        __syncthreads();
-    }
-
-    uint32_t prefix = 0u, mask = 0u;
-    uint32_t need = static_cast<uint32_t>(K);
-    for (int32_t shift = 24; shift >= 0; shift -= 8) {
-        for (int32_t i = tid; i < 256; i += kTopThreads) hist[i] = 0u;
-        __syncthreads();
-        for (int32_t i = tid; i < n; i += kTopThreads) {
-            const uint32_t k = bits[i];
-            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 0xFFu], 1u);
-        }
-        __syncthreads();
-        if (tid < kWave) {
-            // the digit d holding the need-th largest, counting from the top
-            // bin down: lane l holds bins 4l .. 4l+3; the last lane whose
-            // bins and all above reach `need` holds d
-            const uint4 h = reinterpret_cast<const uint4*>(hist)[tid];
-            const uint32_t own = h.x + h.y + h.z + h.w;
-            const uint32_t from_here = wave_suffix_sum(own);
-            const uint64_t reach = __ballot(from_here >= need);
-            if (tid == 63 - __builtin_clzll(reach)) {
-                uint32_t above = from_here - own;  // entries in the bins above lane tid's
-                const uint32_t bins[4] = {h.x, h.y, h.z, h.w};
-                int32_t q = 3;
-                for (; q > 0; --q) {
-                    if (above + bins[q] >= need) break;
-                    above += bins[q];
-                }
-                misc[0] = static_cast<uint32_t>(4 * tid + q);
-                misc[1] = above;
-            }
-        }
-        __syncthreads();
-        prefix |= misc[0] << shift;
-        mask |= 0xFFu << shift;
-        need -= misc[1];
-        __syncthreads();
-    }
-    const uint32_t T = prefix;  // `need` (>= 1) entries equal to T complete the top K
-
-    // rank the entries equal to T in city order: contiguous segments per thread
-    const int32_t seg = (n + kTopThreads - 1) / kTopThreads;
-    const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
-    uint32_t eq = 0u;
-    for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
-    // exclusive prefix sum of the segment counts in thread order: within each
-    // wavefront, then the totals of the wavefronts before it
-    const uint32_t incl = wave_prefix_sum(eq);
-    if ((tid & (kWave - 1)) == kWave - 1) seg_count[tid / kWave] = incl;
-    if (tid == 0) misc[2] = 0u;
-    __syncthreads();
-    uint32_t rank = incl - eq;
-    for (int32_t w = 0; w < tid / kWave; ++w) rank += seg_count[w];
-    // entries above T take slots need .. K-1 (their order is fixed by the sort
-    // below); the equal ones of rank < need take slots 0 .. need-1
-    for (int32_t i = lo; i < hi; ++i) {
-        const uint32_t k = bits[i];
-        int32_t slot = -1;
-        if (k > T) {
-            slot = static_cast<int32_t>(need + atomicAdd(&misc[2], 1u));
-        } else if (k == T) {
-            if (rank < need) slot = static_cast<int32_t>(rank);
-            ++rank;
-        }
-        if (slot >= 0 && slot < K) {
-            key[slot] = k;
-            city[slot] = static_cast<uint16_t>(i);
-        }
-    }
-    __syncthreads();
-    bitonic_lds(key, city, K);
-    const size_t out = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(K);
-    for (int32_t i = tid; i < K; i += kTopThreads) {
-        Ps[out + i] = __uint_as_float(key[i]);
-        Js[out + i] = city[i];
-    }
-}
-
 // Bitonic network over N = 64 * REGS entries held in registers: entry e sits
 // in register e / 64 of lane e mod 64.  An entry is one 64-bit key, the
 // value's bits above (0xFFFF - city), so that the larger key is the one that
@@ -255,6 +138,221 @@ __device__ __forceinline__ void bitonic_wave(uint64_t (&v)[REGS]) {
                 }
             }
         }
+    }
+}
+
+// The K = 64 * REGS (key, city) slots in LDS sorted by one wavefront (value
+// descending, then city ascending, as bitonic_lds orders them) and written out.
+template <int REGS>
+__device__ __forceinline__ void sort_slots_wave(const uint32_t* key, const uint16_t* city,
+                                                float* __restrict__ out_p,
+                                                uint16_t* __restrict__ out_j) {
+    const int32_t lane = threadIdx.x & 63;
+    uint64_t v[REGS];
+#pragma unroll
+    for (int32_t r = 0; r < REGS; ++r) {
+        const int32_t e = r * 64 + lane;
+        v[r] = (static_cast<uint64_t>(key[e]) << 32) |
+               static_cast<uint64_t>(0xFFFFu - static_cast<uint32_t>(city[e]));
+    }
+    bitonic_wave<REGS>(v);
+#pragma unroll
+    for (int32_t r = 0; r < REGS; ++r) {
+        const int32_t e = r * 64 + lane;
+        out_p[e] = __uint_as_float(static_cast<uint32_t>(v[r] >> 32));
+        out_j[e] = static_cast<uint16_t>(0xFFFFu - static_cast<uint32_t>(v[r] & 0xFFFFu));
+    }
+}
+
+// Largest K that one wavefront sorts in registers (16 entries per lane).
+constexpr int32_t kTopWaveSortMax = 1024;
+
+// Radix digits of the top-K select, most significant first: 9 + 8 + 8 + 7
+// bits.  The first digit is the sign and the whole exponent, so that the
+// entries of a row, whose values span many binades, spread over many bins.
+constexpr int32_t kTopBins = 512;
+constexpr int32_t kDigitShift[4] = {23, 15, 7, 0};
+constexpr int32_t kDigitBits[4] = {9, 8, 8, 7};
+
+// LDS bytes of topk_rows_kernel before the row itself: histogram, segment
+// counts, scalars, then the K (key, city) slots.
+constexpr size_t topk_lds_bytes(int32_t K) {
+    return sizeof(uint32_t) * (kTopBins + kTopThreads + 4) +
+           static_cast<size_t>(K) * (sizeof(uint32_t) + sizeof(uint16_t));
+}
+static_assert(topk_lds_bytes(8) % 16 == 0, "the staged row must start on a 16-byte boundary");
+
+// LDS bytes of the staged row: n entries rounded up to whole 16-byte blocks.
+constexpr size_t topk_staged_bytes(int32_t n) {
+    return sizeof(uint32_t) * static_cast<size_t>((n + 3) & ~3);
+}
+
+// 16-byte loads in flight per thread while a row is staged.
+constexpr int32_t kStageLoads = 8;
+// Largest dynamic LDS a top-K launch asks for (the full sort's 16384 slots
+// use as much); rows that would need more are read from global memory.
+constexpr size_t kTopStagedMax = 16384 * (sizeof(uint32_t) + sizeof(uint16_t)) +
+                                 sizeof(uint32_t) * (kTopBins + kTopThreads + 4);
+
+// The first K entries of the full sort of a row, for K < n (K a power of two):
+// every entry whose key exceeds the K-th largest key T, and the entries equal
+// to T with the smallest cities, then sorted.  T is found by a radix select,
+// most significant byte first: four 256-bin LDS histograms over the entries
+// that match the bytes chosen so far.  The entries equal to T are ranked in
+// city order through per-thread contiguous segments and a prefix sum.  With
+// STAGED the row is first copied to LDS (one coalesced pass), and every later
+// pass reads it there.
+template <bool STAGED>
+__global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __restrict__ P,
+                                                                int32_t n, int32_t ld,
+                                                                int32_t K,
+                                                                float* __restrict__ Ps,
+                                                                uint16_t* __restrict__ Js) {
+    extern __shared__ uint32_t sh[];
+    uint32_t* hist = sh;                                          // kTopBins
+    uint32_t* seg_count = sh + kTopBins;                          // one per wavefront
+    uint32_t* misc = sh + kTopBins + kTopThreads;                 // 4
+    uint32_t* key = sh + kTopBins + kTopThreads + 4;              // K
+    uint16_t* city = reinterpret_cast<uint16_t*>(key + K);        // K
+    const size_t row = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(ld);
+    const int32_t tid = threadIdx.x;
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(P + row);
+    if constexpr (STAGED) {
+        // 16-byte blocks: the row starts on a 256-byte boundary and its
+        // padding (P = 0) reaches at least the next multiple of 4 entries; the
+        // staged copy starts on a 16-byte boundary (K is a multiple of 8) and
+        // has room for that many.  Each thread issues all its loads before
+        // its first LDS store, so it waits for memory once per kStageLoads.
+        uint32_t* staged = reinterpret_cast<uint32_t*>(city + K);
+        const int32_t nq = (n + 3) >> 2;
+        const uint4* src = reinterpret_cast<const uint4*>(bits);
+        uint4* dst = reinterpret_cast<uint4*>(staged);
+        for (int32_t q0 = tid; q0 < nq; q0 += kTopThreads * kStageLoads) {
+            uint4 v[kStageLoads];
+#pragma unroll
+            for (int32_t u = 0; u < kStageLoads; ++u) {
+                const int32_t q = q0 + u * kTopThreads;
+                if (q < nq) v[u] = src[q];
+            }
+#pragma unroll
+            for (int32_t u = 0; u < kStageLoads; ++u) {
+                const int32_t q = q0 + u * kTopThreads;
+                if (q < nq) dst[q] = v[u];
+            }
+        }
+        bits = staged;
+        __syncthreads();
+    }
+
+    uint32_t prefix = 0u, mask = 0u;
+    uint32_t need = static_cast<uint32_t>(K);
+#pragma unroll
+    for (int32_t pass = 0; pass < 4; ++pass) {
+        const int32_t shift = kDigitShift[pass];
+        const int32_t nbins = 1 << kDigitBits[pass];
+        const uint32_t digit_mask = static_cast<uint32_t>(nbins - 1);
+        for (int32_t i = tid; i < nbins; i += kTopThreads) hist[i] = 0u;
+        __syncthreads();
+        for (int32_t i = tid; i < n; i += kTopThreads) {
+            const uint32_t k = bits[i];
+            if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & digit_mask], 1u);
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            // the digit d holding the need-th largest, counting from the top
+            // bin down: lane l holds bins B*l .. B*l+B-1; the last lane whose
+            // bins and all above reach `need` holds d
+            constexpr int32_t kMaxPerLane = kTopBins / kWave;
+            const int32_t per_lane = nbins / kWave;
+            uint32_t h[kMaxPerLane];
+            uint32_t own = 0u;
+#pragma unroll
+            for (int32_t q = 0; q < kMaxPerLane; ++q) {
+                h[q] = q < per_lane ? hist[tid * per_lane + q] : 0u;
+                own += h[q];
+            }
+            const uint32_t from_here = wave_suffix_sum(own);
+            const uint64_t reach = __ballot(from_here >= need);
+            if (tid == 63 - __builtin_clzll(reach)) {
+                uint32_t above = from_here - own;  // entries in the bins above lane tid's
+                int32_t q = per_lane - 1;
+                for (; q > 0; --q) {
+                    if (above + h[q] >= need) break;
+                    above += h[q];
+                }
+                misc[0] = static_cast<uint32_t>(tid * per_lane + q);
+                misc[1] = above;
+            }
+        }
+        __syncthreads();
+        prefix |= misc[0] << shift;
+        mask |= digit_mask << shift;
+        need -= misc[1];
+        __syncthreads();
+    }
+    const uint32_t T = prefix;  // `need` (>= 1) entries equal to T complete the top K
+
+    // rank the entries equal to T in city order: contiguous segments per thread
+    const int32_t seg = (n + kTopThreads - 1) / kTopThreads;
+    const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
+    uint32_t eq = 0u;
+    for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
+    // exclusive prefix sum of the segment counts in thread order: within each
+    // wavefront, then the totals of the wavefronts before it
+    const uint32_t incl = wave_prefix_sum(eq);
+    if ((tid & (kWave - 1)) == kWave - 1) seg_count[tid / kWave] = incl;
+    if (tid == 0) misc[2] = 0u;
+    __syncthreads();
+    uint32_t rank = incl - eq;
+    for (int32_t w = 0; w < tid / kWave; ++w) rank += seg_count[w];
+    // entries above T take slots need .. K-1 (their order is fixed by the sort
+    // below), a wavefront's at a time from one counter; the equal ones of
+    // rank < need take slots 0 .. need-1
+    const int32_t lane = tid & (kWave - 1);
+    for (int32_t u = 0; u < seg; ++u) {
+        const int32_t i = lo + u;
+        const uint32_t k = i < hi ? bits[i] : 0u;
+        const bool above = i < hi && k > T;
+        const uint64_t took = __ballot(above);
+        uint32_t base = 0u;
+        if (lane == 0 && took) base = atomicAdd(&misc[2], static_cast<uint32_t>(__popcll(took)));
+        base = static_cast<uint32_t>(__shfl(static_cast<int32_t>(base), 0));
+        int32_t slot = -1;
+        if (above) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(took >> 32),
+                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(took), 0u));
+            slot = static_cast<int32_t>(need + base + below);
+        } else if (i < hi && k == T) {
+            if (rank < need) slot = static_cast<int32_t>(rank);
+            ++rank;
+        }
+        if (slot >= 0 && slot < K) {
+            key[slot] = k;
+            city[slot] = static_cast<uint16_t>(i);
+        }
+    }
+    __syncthreads();
+    const size_t out = static_cast<size_t>(blockIdx.x) * static_cast<size_t>(K);
+    if (K <= kTopWaveSortMax) {
+        // one wavefront sorts the K slots in registers, with no barrier
+        if (tid < kWave) {
+            float* op = Ps + out;
+            uint16_t* oj = Js + out;
+            switch (K) {
+                case 64: sort_slots_wave<1>(key, city, op, oj); break;
+                case 128: sort_slots_wave<2>(key, city, op, oj); break;
+                case 256: sort_slots_wave<4>(key, city, op, oj); break;
+                case 512: sort_slots_wave<8>(key, city, op, oj); break;
+                default: sort_slots_wave<16>(key, city, op, oj); break;
+            }
+        }
+        return;
+    }
+    bitonic_lds(key, city, K);
+    for (int32_t i = tid; i < K; i += kTopThreads) {
+        Ps[out + i] = __uint_as_float(key[i]);
+        Js[out + i] = city[i];
     }
 }
 
@@ -343,7 +441,7 @@ hipError_t launch_sort_rows(const float* P, int32_t n, int32_t ld, int32_t walk,
     const int32_t K = sorted_prefix(n, walk);
     if (K < n) {
         const size_t lds = topk_lds_bytes(K);
-        const size_t staged = lds + sizeof(uint32_t) * static_cast<size_t>(n);
+        const size_t staged = lds + topk_staged_bytes(n);
         if (staged <= kTopStagedMax) {
             hipLaunchKernelGGL(topk_rows_kernel<true>, dim3(n), dim3(kTopThreads), staged, stream,
                                P, n, ld, K, Ps, Js);

@@ -114,6 +114,28 @@ def test_sorted_walk_converged_pheromone():
     col.close()
 
 
+@pytest.mark.parametrize("beta", [2.0, 40.0])
+def test_top_k_prefixes_every_size(beta):
+    """Every row's kept prefix at K = 64 ... 2048 (one wavefront sorts the K
+    selected entries in registers up to K = 1024, the LDS network above), on
+    ordinary rows and on rows that are mostly zeros, where the K-th value is
+    0 and many entries tie with it (ties go to the smaller city)."""
+    torch = _torch()
+    n = 2100
+    D = inst.distance_matrix(inst.clustered_cities(n, 15, 11, 0.02))
+    col = _colony(D, 1.0, beta, 0.2, 8)
+    col.set_selection("adair-sorted")
+    for walk in (1, 2, 4, 8, 16, 32):
+        col.set_sorted_walk(walk)
+        col.transition(1.0)
+        col.sync()
+        P = col.P().cpu().numpy()
+        if beta > 2.0:
+            assert np.mean(P == 0) > 0.9  # the K-th value is 0 in most rows
+        _check_sorted_rows(col, P, walk)
+    col.close()
+
+
 def test_sorted_walk_zero_and_subnormal_rows():
     torch = _torch()
     n, m = 300, 48
