@@ -76,32 +76,50 @@ __device__ __forceinline__ double row_max_all(double v, double* red) {
     return v;
 }
 
-// Sum over j of f(j) for j < n with a fixed association, whatever T is: each
-// 64-column chunk is summed by a 64-lane butterfly (every lane gets the same
-// bits: IEEE addition is commutative), then the chunk sums are added in chunk
-// order starting from +0.  One instance and a batch therefore build
-// bit-identical rows.
+// Sum over j < n of f(j) in one fixed association for T = 64 and T = 512, so
+// that one instance and a batch build bit-identical rows.  Column chunk
+// c = j / 64 feeds partial (c mod 8, j mod 64), which adds its terms in
+// ascending c from +0; each lane then adds its 8 partials in order, and the
+// 64 lane totals meet in a butterfly (every lane gets the same bits: IEEE
+// addition is commutative).  One LDS read and one add per term.
+constexpr int32_t kSumGroups = 8;
+
 template <int T, typename F>
 __device__ __forceinline__ double row_sum_fixed(int32_t n, F f, double* partial) {
+    static_assert(T == 64 || T == 64 * kSumGroups, "one wavefront, or one per partial group");
     const int32_t lane = threadIdx.x & 63;
-    const int32_t wave = (threadIdx.x & (T - 1)) >> 6;
     const int32_t nchunks = (n + 63) >> 6;
-    double total = 0.0;
-    for (int32_t c = wave; c < nchunks; c += T / 64) {
-        const int32_t j = (c << 6) + lane;
-        const double chunk = wave_sum(j < n ? f(j) : 0.0);
-        if constexpr (T == 64) {
-            total += chunk;
-        } else {
-            if (lane == 0) partial[c] = chunk;
+    if constexpr (T == 64) {
+        double s[kSumGroups];
+#pragma unroll
+        for (int32_t w = 0; w < kSumGroups; ++w) s[w] = 0.0;
+        for (int32_t c0 = 0; c0 < nchunks; c0 += kSumGroups) {
+#pragma unroll
+            for (int32_t w = 0; w < kSumGroups; ++w) {
+                const int32_t j = ((c0 + w) << 6) + lane;
+                if (j < n) s[w] += f(j);
+            }
         }
-    }
-    if constexpr (T > 64) {
+        double t = s[0];
+#pragma unroll
+        for (int32_t w = 1; w < kSumGroups; ++w) t += s[w];
+        return wave_sum(t);
+    } else {
+        const int32_t wave = threadIdx.x >> 6;
+        double s = 0.0;
+        for (int32_t c = wave; c < nchunks; c += kSumGroups) {
+            const int32_t j = (c << 6) + lane;
+            if (j < n) s += f(j);
+        }
+        partial[wave * 64 + lane] = s;
         __syncthreads();
-        for (int32_t c = 0; c < nchunks; ++c) total += partial[c];
+        double t = partial[lane];
+#pragma unroll
+        for (int32_t w = 1; w < kSumGroups; ++w) t += partial[w * 64 + lane];
+        const double total = wave_sum(t);
         __syncthreads();
+        return total;
     }
-    return total;
 }
 
 struct RowArgs {
@@ -340,7 +358,7 @@ __global__ __launch_bounds__(kRowThreads) void row_kernel(
     const int64_t* __restrict__ weight, int32_t apply_deposit, double keep, double unit,
     double alpha, double beta, double gamma, float tau_min, float tau_max) {
     extern __shared__ double lnw[];
-    __shared__ double red[ACO_LDS_ROW_MAX / 64];  // wave maxima, then chunk sums
+    __shared__ double red[64 * kSumGroups];  // wave maxima, then the sum's partials
     const int32_t i = blockIdx.x;
     const size_t off = static_cast<size_t>(i) * ld;
     RowArgs a;
