@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include "construct.hpp"
+#include "fp64_math.hpp"
 
 namespace aco {
 
@@ -147,73 +148,10 @@ __device__ __forceinline__ double int_power(double x, int32_t k) {
     return r;
 }
 
-// ln 2 in two parts (Cody and Waite): the high part has 24 trailing zero bits,
-// so k * kLn2Hi is exact for every k used here.
-constexpr double kLn2Hi = 0x1.62e42ffp-1;
-constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
-constexpr double kLog2E = 0x1.71547652b82fep+0;
-
-// Natural logarithm of a positive finite x.  With x = m 2^e, m in
-// [sqrt(1/2), sqrt(2)), ln x = e ln 2 + 2 atanh(t) for t = (m - 1) / (m + 1),
-// |t| < 0.172; the odd series of atanh is summed to t^19 (the first term left
-// out is below 1e-17).  Absolute error below 1e-13 over the FP64 range, which
-// is all the power form needs: P is a difference of two such logarithms,
-// exponentiated and rounded to FP32.
-__device__ __forceinline__ double ln_positive(double x) {
-    int32_t e;
-    double m = frexp(x, &e);  // [0.5, 1)
-    if (m < 0.70710678118654752) {
-        m *= 2.0;
-        e -= 1;
-    }
-    // 1 / (m + 1) by the hardware reciprocal and two Newton steps (each
-    // squares the relative error), enough for t to within a few ulp
-    const double d = m + 1.0;
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
-    const double t = (m - 1.0) * r;
-    const double s = t * t;
-    double q = 1.0 / 19.0;
-    q = fma(q, s, 1.0 / 17.0);
-    q = fma(q, s, 1.0 / 15.0);
-    q = fma(q, s, 1.0 / 13.0);
-    q = fma(q, s, 1.0 / 11.0);
-    q = fma(q, s, 1.0 / 9.0);
-    q = fma(q, s, 1.0 / 7.0);
-    q = fma(q, s, 1.0 / 5.0);
-    q = fma(q, s, 1.0 / 3.0);
-    q = fma(q, s, 1.0);
-    const double de = static_cast<double>(e);
-    return fma(de, kLn2Hi, fma(de, kLn2Lo, 2.0 * t * q));
-}
-
-// e^y for y <= 0 (or a rounding error above it), for a result that is then
-// rounded to FP32: y = k ln 2 + r with k = rint(y / ln 2), |r| <= ln 2 / 2,
-// e^r by its Taylor series to r^13 (the first term left out is below 4e-18),
-// scaled by 2^k.  Below -200 it returns 0: e^-200 is far under half the
-// smallest FP32 subnormal.
-__device__ __forceinline__ double exp_for_f32(double y) {
-    if (y < -200.0) return 0.0;
-    const double k = rint(y * kLog2E);
-    double r = fma(-k, kLn2Hi, y);
-    r = fma(-k, kLn2Lo, r);
-    double p = 1.0 / 6227020800.0;
-    p = fma(p, r, 1.0 / 479001600.0);
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
-    p = fma(p, r, 1.0 / 5040.0);
-    p = fma(p, r, 1.0 / 720.0);
-    p = fma(p, r, 1.0 / 120.0);
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, 1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return ldexp(p, static_cast<int32_t>(k));
-}
+// 1/d seed for ln_positive: the hardware FP64 reciprocal.
+struct HardwareRcp {
+    __device__ double operator()(double d) const { return __builtin_amdgcn_rcp(d); }
+};
 
 template <int T>
 __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
@@ -317,13 +255,13 @@ __device__ void update_row(const RowArgs& a, double* lnw, double* red) {
             }
         } else if (total > 0.0 && total < INFINITY) {
             // every W is finite and at most the sum; W = 0 gives P = 0
-            const double ln_total = ln_positive(total);
+            const double ln_total = ln_positive(total, HardwareRcp{});
             const double inv_gamma = 1.0 / a.gamma;
             for (int32_t j = tid; j < a.ld; j += T) {
                 float p = 0.0f;
                 if (j < a.n && j != a.i && lnw[j] > 0.0)
                     p = static_cast<float>(
-                        exp_for_f32((ln_positive(lnw[j]) - ln_total) * inv_gamma));
+                        exp_for_f32((ln_positive(lnw[j], HardwareRcp{}) - ln_total) * inv_gamma));
                 a.P[j] = p;
             }
         } else {
