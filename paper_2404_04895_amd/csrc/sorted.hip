@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
                 }
                 misc[0] = static_cast<uint32_t>(tid * per_lane + q);
                 misc[1] = above;
+                misc[3] = h[q];  // entries in the chosen bin
             }
         }
         __syncthreads();
@@ -291,45 +292,70 @@ __global__ __launch_bounds__(kTopThreads) void topk_rows_kernel(const float* __r
         __syncthreads();
     }
     const uint32_t T = prefix;  // `need` (>= 1) entries equal to T complete the top K
-
-    // rank the entries equal to T in city order: contiguous segments per thread
-    const int32_t seg = (n + kTopThreads - 1) / kTopThreads;
-    const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
-    uint32_t eq = 0u;
-    for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
-    // exclusive prefix sum of the segment counts in thread order: within each
-    // wavefront, then the totals of the wavefronts before it
-    const uint32_t incl = wave_prefix_sum(eq);
-    if ((tid & (kWave - 1)) == kWave - 1) seg_count[tid / kWave] = incl;
-    if (tid == 0) misc[2] = 0u;
-    __syncthreads();
-    uint32_t rank = incl - eq;
-    for (int32_t w = 0; w < tid / kWave; ++w) rank += seg_count[w];
-    // entries above T take slots need .. K-1 (their order is fixed by the sort
-    // below), a wavefront's at a time from one counter; the equal ones of
-    // rank < need take slots 0 .. need-1
     const int32_t lane = tid & (kWave - 1);
-    for (int32_t u = 0; u < seg; ++u) {
-        const int32_t i = lo + u;
-        const uint32_t k = i < hi ? bits[i] : 0u;
-        const bool above = i < hi && k > T;
-        const uint64_t took = __ballot(above);
-        uint32_t base = 0u;
-        if (lane == 0 && took) base = atomicAdd(&misc[2], static_cast<uint32_t>(__popcll(took)));
-        base = static_cast<uint32_t>(__shfl(static_cast<int32_t>(base), 0));
-        int32_t slot = -1;
-        if (above) {
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                static_cast<uint32_t>(took >> 32),
-                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(took), 0u));
-            slot = static_cast<int32_t>(need + base + below);
-        } else if (i < hi && k == T) {
-            if (rank < need) slot = static_cast<int32_t>(rank);
-            ++rank;
+    if (misc[3] == need) {
+        // every entry equal to T is kept (the usual case: T is unique), so no
+        // ranking is needed: all entries >= T take slots, a wavefront's at a
+        // time from one counter, in any order (the sort below orders them)
+        if (tid == 0) misc[2] = 0u;
+        __syncthreads();
+        for (int32_t i0 = 0; i0 < n; i0 += kTopThreads) {
+            const int32_t i = i0 + tid;
+            const uint32_t k = i < n ? bits[i] : 0u;
+            const bool kept = i < n && k >= T;
+            const uint64_t took = __ballot(kept);
+            uint32_t base = 0u;
+            if (lane == 0 && took) base = atomicAdd(&misc[2], static_cast<uint32_t>(__popcll(took)));
+            base = static_cast<uint32_t>(__shfl(static_cast<int32_t>(base), 0));
+            if (kept) {
+                const uint32_t slot = base + __builtin_amdgcn_mbcnt_hi(
+                    static_cast<uint32_t>(took >> 32),
+                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(took), 0u));
+                if (slot < static_cast<uint32_t>(K)) {
+                    key[slot] = k;
+                    city[slot] = static_cast<uint16_t>(i);
+                }
+            }
         }
-        if (slot >= 0 && slot < K) {
-            key[slot] = k;
-            city[slot] = static_cast<uint16_t>(i);
+    } else {
+        // rank the entries equal to T in city order: contiguous segments per thread
+        const int32_t seg = (n + kTopThreads - 1) / kTopThreads;
+        const int32_t lo = min(n, tid * seg), hi = min(n, lo + seg);
+        uint32_t eq = 0u;
+        for (int32_t i = lo; i < hi; ++i) eq += (bits[i] == T) ? 1u : 0u;
+        // exclusive prefix sum of the segment counts in thread order: within each
+        // wavefront, then the totals of the wavefronts before it
+        const uint32_t incl = wave_prefix_sum(eq);
+        if ((tid & (kWave - 1)) == kWave - 1) seg_count[tid / kWave] = incl;
+        if (tid == 0) misc[2] = 0u;
+        __syncthreads();
+        uint32_t rank = incl - eq;
+        for (int32_t w = 0; w < tid / kWave; ++w) rank += seg_count[w];
+        // entries above T take slots need .. K-1 (their order is fixed by the sort
+        // below), a wavefront's at a time from one counter; the equal ones of
+        // rank < need take slots 0 .. need-1
+        for (int32_t u = 0; u < seg; ++u) {
+            const int32_t i = lo + u;
+            const uint32_t k = i < hi ? bits[i] : 0u;
+            const bool above = i < hi && k > T;
+            const uint64_t took = __ballot(above);
+            uint32_t base = 0u;
+            if (lane == 0 && took) base = atomicAdd(&misc[2], static_cast<uint32_t>(__popcll(took)));
+            base = static_cast<uint32_t>(__shfl(static_cast<int32_t>(base), 0));
+            int32_t slot = -1;
+            if (above) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    static_cast<uint32_t>(took >> 32),
+                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(took), 0u));
+                slot = static_cast<int32_t>(need + base + below);
+            } else if (i < hi && k == T) {
+                if (rank < need) slot = static_cast<int32_t>(rank);
+                ++rank;
+            }
+            if (slot >= 0 && slot < K) {
+                key[slot] = k;
+                city[slot] = static_cast<uint16_t>(i);
+            }
         }
     }
     __syncthreads();
