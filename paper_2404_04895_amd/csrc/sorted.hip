@@ -99,46 +99,97 @@ __device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t v) {
     return v;
 }
 
+// v of lane (lane ^ S), S a power of two below 64, without going through
+// LDS: quad permutations for 1 and 2; row rotations for 4 and 8 (row_ror:N
+// gives lane l the value of lane (l - N) mod 16 of its row of 16, so lane l
+// takes l - 4 when bit 2 of l is set and l + 4 = l - 12 otherwise); the
+// permlane16 / permlane32 swaps for 16 and 32 (swapping v with itself, the
+// first result holds, in the upper row or half of each pair, the lower
+// one's values, and the second result the other way round).
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    const int32_t lane = threadIdx.x & 63;
+    const int32_t x = static_cast<int32_t>(v);
+    if constexpr (S == 1) {
+        return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));
+    } else if constexpr (S == 2) {
+        return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));
+    } else if constexpr (S == 4) {
+        const int32_t down = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // l - 4
+        const int32_t up = __builtin_amdgcn_update_dpp(0, x, 0x12C, 0xF, 0xF, false);    // l + 4
+        return static_cast<uint32_t>((lane & 4) ? down : up);
+    } else if constexpr (S == 8) {
+        return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    } else if constexpr (S == 16) {
+        const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? sw[0] : sw[1];
+    } else {
+        static_assert(S == 32, "S is a power of two below 64");
+        const auto sw = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? sw[0] : sw[1];
+    }
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v) {
+    const uint32_t lo = xor_lane<S>(static_cast<uint32_t>(v));
+    const uint32_t hi = xor_lane<S>(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Bitonic network over N = 64 * REGS entries held in registers: entry e sits
 // in register e / 64 of lane e mod 64.  An entry is one 64-bit key, the
 // value's bits above (0xFFFF - city), so that the larger key is the one that
 // comes first (value descending, then city ascending, as in bitonic_lds) and
 // an empty slot (key 0) comes last.  Partners at a stride of 64 or more are in
 // the same lane; nearer ones are exchanged across lanes.
-template <int REGS>
-__device__ __forceinline__ void bitonic_wave(uint64_t (&v)[REGS]) {
+// One stage of the network: compare-exchange at distance STRIDE within
+// bitonic runs of SIZE entries (SIZE and STRIDE are template arguments, so
+// every lane exchange has its permutation as an immediate).
+template <int REGS, int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_stage(uint64_t (&v)[REGS]) {
     const int32_t lane = threadIdx.x & 63;
+    if constexpr (STRIDE >= 64) {
+        constexpr int32_t rs = STRIDE / 64;
 #pragma unroll
-    for (int32_t size = 2; size <= 64 * REGS; size <<= 1) {
+        for (int32_t r = 0; r < REGS; ++r) {
+            if (r & rs) continue;  // r holds the lower entry of the pair (r, r | rs)
+            const int32_t r2 = r | rs;
+            const bool down = ((r * 64 + lane) & SIZE) == 0;
+            const uint64_t hi = max(v[r], v[r2]), lo = min(v[r], v[r2]);
+            v[r] = down ? hi : lo;
+            v[r2] = down ? lo : hi;
+        }
+    } else {
+        const bool lower = (lane & STRIDE) == 0;
 #pragma unroll
-        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            if (stride >= 64) {
-                const int32_t rs = stride >> 6;
-#pragma unroll
-                for (int32_t r = 0; r < REGS; ++r) {
-                    if (r & rs) continue;  // r holds the lower entry of the pair (r, r | rs)
-                    const int32_t r2 = r | rs;
-                    const bool down = ((r * 64 + lane) & size) == 0;
-                    const uint64_t hi = max(v[r], v[r2]), lo = min(v[r], v[r2]);
-                    v[r] = down ? hi : lo;
-                    v[r2] = down ? lo : hi;
-                }
-            } else {
-                const bool lower = (lane & stride) == 0;
-#pragma unroll
-                for (int32_t r = 0; r < REGS; ++r) {
-                    const uint64_t p = static_cast<uint64_t>(
-                        __shfl_xor(static_cast<unsigned long long>(v[r]), stride));
-                    const bool down = ((r * 64 + lane) & size) == 0;
-                    // the lower entry of a descending pair keeps the larger key:
-                    // take the partner's if it is on the wanted side (when the
-                    // keys are equal, either is the same)
-                    const bool keeps_larger = lower == down;
-                    if ((p > v[r]) == keeps_larger) v[r] = p;
-                }
-            }
+        for (int32_t r = 0; r < REGS; ++r) {
+            const uint64_t p = xor_lane64<STRIDE>(v[r]);
+            const bool down = ((r * 64 + lane) & SIZE) == 0;
+            // the lower entry of a descending pair keeps the larger key:
+            // take the partner's if it is on the wanted side (when the keys
+            // are equal, either is the same)
+            const bool keeps_larger = lower == down;
+            if ((p > v[r]) == keeps_larger) v[r] = p;
         }
     }
+}
+
+template <int REGS, int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_merge(uint64_t (&v)[REGS]) {
+    bitonic_stage<REGS, SIZE, STRIDE>(v);
+    if constexpr (STRIDE > 1) bitonic_merge<REGS, SIZE, STRIDE / 2>(v);
+}
+
+template <int REGS, int SIZE>
+__device__ __forceinline__ void bitonic_sizes(uint64_t (&v)[REGS]) {
+    bitonic_merge<REGS, SIZE, SIZE / 2>(v);
+    if constexpr (SIZE < 64 * REGS) bitonic_sizes<REGS, SIZE * 2>(v);
+}
+
+template <int REGS>
+__device__ __forceinline__ void bitonic_wave(uint64_t (&v)[REGS]) {
+    bitonic_sizes<REGS, 2>(v);
 }
 
 // The K = 64 * REGS (key, city) slots in LDS sorted by one wavefront (value
