@@ -450,6 +450,10 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
     const int32_t limit = min(64 * I.walk, I.n);
     const bool ahead = spec.city == cur;
     for (int32_t base = 0; base < limit; base += G) {
+        // the step's first entries, their visited bits and the next
+        // speculative load form the chain every step waits on: issue them
+        // ahead of other wavefronts' deviates
+        if (base == 0) __builtin_amdgcn_s_setprio(2);
         const int32_t pos = base + gl;
         float p = 0.0f;
         int32_t j = -1;
@@ -474,6 +478,7 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
                 spec.p = sorted_p(R, next);
                 spec.j = sorted_j(R, next);
             }
+            __builtin_amdgcn_s_setprio(0);
         }
         if (cand) {
             const PhiloxOut r = philox10_block(static_cast<uint32_t>(j >> 2),
