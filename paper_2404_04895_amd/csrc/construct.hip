@@ -496,6 +496,8 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
             }
         }
         entries_read += static_cast<uint32_t>(G);
+        // the decision gates the next step: ahead of other deviates too
+        __builtin_amdgcn_s_setprio(1);
         const int32_t top = group_reduce<G, true>(best_key);
         const float p_last = __int_as_float(group_lane<G>(__float_as_int(p), G - 1));
         if (top >= 0 && p_last < __int_as_float(top))
