@@ -606,9 +606,12 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
             } else {
                 // AHEAD chunks of G blocks are loaded before any is scored, so
                 // that a lane waits for memory once per AHEAD chunks
+                // (the loads at a higher priority than other wavefronts'
+                // scoring, the group's decision between the two)
                 for (int32_t base = 0; base < span; base += AHEAD * G) {
                     float4 pv[AHEAD];
                     int32_t bv[AHEAD];
+                    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                     for (int32_t u = 0; u < AHEAD; ++u) {
                         const int32_t pos = base + u * G + gl;
@@ -618,11 +621,13 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
                             pv[u] = matrix_block(rows, row_e, bv[u]);
                         }
                     }
+                    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                     for (int32_t u = 0; u < AHEAD; ++u) {
                         if (bv[u] >= 0) score_block(bv[u], pv[u]);
                     }
                 }
+                __builtin_amdgcn_s_setprio(1);
             }
             // Group argmax: the largest key, and among equal keys the smallest city.
             const int32_t top = group_reduce<G, true>(best_key);
