@@ -288,10 +288,13 @@ __device__ __forceinline__ size_t row_offset(int32_t c, int32_t ld) {
 }
 
 // Chunks of the row a scanning step loads before it scores the first: four
-// where a scan is latency-bound (the sorted walk's rare fallback, the small
-// instances of a batch), one for the full scan of one large instance, which
-// is bound by HBM and slowed by the extra loads in flight.
+// where a scan is latency-bound (the small instances of a batch, the batch's
+// walk fallbacks), eight for the rare fallback of one large instance's walk
+// (its row is long: fewer round trips per scanned step; the batch kernel
+// would pay for the registers everywhere), one for the full scan of one large
+// instance, which is bound by HBM and slowed by the extra loads in flight.
 constexpr int32_t kScanAhead = 4;
+constexpr int32_t kWalkScanAhead = 8;
 
 // ---- per-window output -----------------------------------------------------
 
@@ -697,8 +700,9 @@ __global__ __launch_bounds__(kWave) void construct_kernel(InstanceView I, int32_
     extern __shared__ uint32_t lds[];
     constexpr int32_t kGroups = kWave / G;
     const int32_t ant0 = static_cast<int32_t>(blockIdx.x) * kGroups;
-    construct_group<G, LIVE, SEL, SEL == kSelAdaIR ? 1 : kScanAhead>(I, ant0, min(kGroups, m - ant0),
-                                                                     lds);
+    constexpr int32_t kAhead =
+        SEL == kSelAdaIR ? 1 : (SEL == kSelSorted ? kWalkScanAhead : kScanAhead);
+    construct_group<G, LIVE, SEL, kAhead>(I, ant0, min(kGroups, m - ant0), lds);
 }
 
 __global__ void uniforms_kernel(uint32_t key0, uint32_t key1, uint32_t iter, uint32_t ant,
