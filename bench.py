@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 COUNTERS_FILES = {"adair": os.path.join(ROOT, "profiles", "construct_counters.json"),
                   "adair-sorted": os.path.join(ROOT, "profiles", "construct_sorted_counters.json")}
 SORTED_MIN_N = 400     # the sorted walk loses at 159 cities and wins at 442 (m = n)
-KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/philox.hpp"]
+KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/construct.hpp",
+                  "paper_2404_04895_amd/csrc/philox.hpp"]
 
 
 def default_selection(n):
