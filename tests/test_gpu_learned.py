@@ -3,8 +3,9 @@
 Bars: ranks bit-exact; mean nearest-neighbour distance bit-exact (same FP64
 sum order); features within one FP32 ulp; z within 1e-4 (1 + |z|) (64-term
 FP32 accumulations on MFMA against FP64, on BF16 operands that are identical on
-both sides); gradients within relative L2 1e-3 of the oracle's FP64 gradient
-at the same BF16 parameters; one Adam step within 1e-6 relative of the
+both sides); gradients within 1e-6 of the oracle's FP64 gradient
+at the same BF16 parameters, block by block (relative L2 and worst
+entry, both 1e-6) on a 16384-edge minibatch; one Adam step within 1e-6 relative of the
 oracle's FP64 step from the same gradient.
 """
 import numpy as np
@@ -82,23 +83,72 @@ def test_eta_matches_oracle():
             assert eta_o[off].std() > 1e-3 * eta_o[off].mean()  # not trivially constant
 
 
-def test_gradient_and_adam_match_oracle():
+BLOCKS = [("W1", 0, 192), ("b1", 192, 256), ("W2", 256, 4352), ("b2", 4352, 4416),
+          ("W3", 4416, 4480), ("b3", 4480, 4481)]
+
+
+def _bf16_np(x):
+    """Nearest-even BF16 rounding of FP32 values (filter helper only)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _away_from_kinks(pb, feats, margin=1e-4):
+    """Edges whose every layer-2 pre-activation is at least `margin` times
+    its own absolute sum away from 0, so that the GPU's FP32 accumulation
+    (about 64 * 2^-24 of that sum) cannot flip a ReLU against the FP64 side.
+    Layer 1 is evaluated in FP64 in the same order on both sides and needs no
+    margin."""
+    W1 = pb[0:192].reshape(64, 3)
+    b1 = pb[192:256]
+    W2 = pb[256:4352].reshape(64, 64)
+    b2 = pb[4352:4416]
+    f = feats.astype(np.float64)
+    a1 = b1[None, :] + f[:, 0:1] * W1[None, :, 0] + f[:, 1:2] * W1[None, :, 1] \
+        + f[:, 2:3] * W1[None, :, 2]
+    h1 = _bf16_np(np.maximum(a1, 0.0).astype(np.float32)).astype(np.float64)
+    a2 = h1 @ W2.T + b2[None, :]
+    scale = np.abs(h1) @ np.abs(W2).T + np.abs(b2)[None, :]
+    return np.all(np.abs(a2) > margin * scale, axis=1)
+
+
+@pytest.mark.parametrize("pseed", [4, 17])
+def test_gradient_and_adam_match_oracle(pseed):
+    """The gradient of a training-size minibatch (16384 edges) block by block:
+    W1, b1, W2, b2, W3 and b3 each within relative L2 1e-6 of the oracle's
+    FP64 gradient, and every entry within 1e-6 of its block's largest
+    magnitude (measured on the GPU: 1e-8 to 4e-8, a few FP32 roundings).  The GPU sums per-edge terms in FP32 over chunks (then FP64
+    across chunks) from FP32 MFMA activations, against FP64 throughout in the
+    oracle, on identical BF16 parameters and BF16 first-layer outputs; edges
+    within reach of a ReLU kink are left out (a flipped mask is a different
+    function, not a rounding error)."""
     torch = _torch()
     from paper_2404_04895_amd import MlpTrainer
-    n = 60
-    D = inst.distance_matrix(inst.clustered_cities(n, 5, 4, 0.05))
+    n = 140
+    D = inst.distance_matrix(inst.clustered_cities(n, 5 + pseed, 4, 0.05))
     F = oracle.edge_features(D)
     off = ~np.eye(n, dtype=bool)
-    feats = F[off].reshape(-1, 3)[:1500]
-    rng = np.random.default_rng(9)
-    y = rng.random(feats.shape[0]).astype(np.float32)
-    p = _init_params(4)
-    t = MlpTrainer(p, batch=2048)
-    g = t.gradient(feats, y).cpu().numpy().astype(np.float64)
+    feats_all = F[off].reshape(-1, 3)
+    p = _init_params(pseed)
     pb = np.array([oracle.bf16_round(v) for v in p], np.float64)
+    keep = _away_from_kinks(pb, feats_all)
+    feats = np.ascontiguousarray(feats_all[keep][:16384])
+    assert feats.shape[0] == 16384, keep.sum()
+    rng = np.random.default_rng(9 + pseed)
+    y = rng.random(feats.shape[0]).astype(np.float32)
+    t = MlpTrainer(p, batch=16384)
+    g = t.gradient(feats, y).cpu().numpy().astype(np.float64)
     loss_o, g_o = oracle.mlp_loss_grad(pb, feats, y, round_bf16=True)
-    rel = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
-    assert rel <= 1e-3, rel
+    for name, lo, hi in BLOCKS:
+        gb, ob = g[lo:hi], g_o[lo:hi]
+        rel = np.linalg.norm(gb - ob) / np.linalg.norm(ob)
+        worst = np.max(np.abs(gb - ob)) / np.max(np.abs(ob))
+        print("block %s: relative L2 %.2e, worst entry %.2e of the block's max" % (name, rel,
+                                                                                   worst))
+        assert np.linalg.norm(ob) > 0, name
+        assert rel <= 1e-6, (name, rel)
+        assert worst <= 1e-6, (name, worst)
     assert abs(t.loss() - loss_o) <= 1e-5 * abs(loss_o)
     # one Adam step from the GPU's gradient
     t.apply(1e-3)

@@ -195,3 +195,56 @@ def test_sorted_walk_full_size_clustered_n5000():
     assert np.array_equal(tours[sample], o_tours)
     assert np.array_equal(lengths[sample].view(np.uint32), o_len.view(np.uint32))
     col.close()
+
+
+def test_sorted_walk_at_the_benchmarked_state_clustered_n5000():
+    """The benchmark workload (5000 clustered cities, 5000 ants, beta 3) driven
+    through its first 25 iterations of the 200-iteration gamma schedule, as
+    the benchmark does, once on the sorted walk and once on the full scan.
+    Every iteration's tours, lengths and pheromone agree bit for bit between
+    the two, and 16 ants spread over the colony at iteration 25 (on pheromone
+    the benchmark's timed iterations see) equal the oracle's AdaIR argmax
+    (Sec. 2.4) on that iteration's P."""
+    torch = _torch()
+    from paper_2404_04895_amd import gamma_schedule
+    w = inst.WORKLOADS["clustered-n5000-m5000"]
+    D = w.dist(0)
+    n, m, T, iters, seed = w.n, w.m, w.iters, 25, 0
+    walk = _colony(D, w.alpha, w.beta, w.rho, m)
+    walk.set_selection("adair-sorted")
+    scan = _colony(D, w.alpha, w.beta, w.rho, m)
+    scan.set_selection("adair")
+    for col in (walk, scan):
+        col.transition(gamma_schedule(0, T, w.gamma_max, w.gamma_min))
+    P_last = None
+    for t in range(iters):
+        if t == iters - 1:
+            walk.sync()
+            P_last = walk.P().cpu().numpy()
+            assert torch.equal(walk.P(), scan.P())
+        for col in (walk, scan):
+            col.construct(m, seed, t)
+        walk.sync()
+        scan.sync()
+        assert torch.equal(walk.tours(m), scan.tours(m)), "tours differ at iteration %d" % t
+        assert torch.equal(walk.lengths(m), scan.lengths(m)), "lengths differ at iteration %d" % t
+        if t == iters - 1:
+            tours = walk.tours(m).cpu().numpy()
+            lengths = walk.lengths(m).cpu().numpy()
+        for col in (walk, scan):
+            col.update(gamma_schedule(t + 1, T, w.gamma_max, w.gamma_min))
+        walk.sync()
+        scan.sync()
+        assert torch.equal(walk.tau(), scan.tau()), "tau differs after iteration %d" % t
+    entries, scanned, _ = walk.sorted_walk_stats()
+    # the walk really decided most steps (converging pheromone, steep rows)
+    assert scanned < 0.05 * iters * m * (n - 1), scanned
+    sample = np.linspace(0, m - 1, 16).astype(np.int64)
+    o_tours, o_len = oracle.construct(P_last, D, seed, iters - 1, sample)
+    assert np.array_equal(tours[sample], o_tours)
+    assert np.array_equal(lengths[sample].view(np.uint32), o_len.view(np.uint32))
+    _, best_walk, it_walk = walk.best()
+    _, best_scan, it_scan = scan.best()
+    assert best_walk == best_scan and it_walk == it_scan
+    walk.close()
+    scan.close()
