@@ -478,6 +478,29 @@ aco_status aco_mlp_trainer_loss(aco_mlp_trainer* t, double* loss_host);
 /* Free the host object.  NULL is a no-op. */
 void aco_mlp_trainer_destroy(aco_mlp_trainer* t);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid it): the
+ * gradient of aco_mlp_trainer_gradient, computed by the same kernels, at the
+ * given BF16 parameters, with no trainer, no workspace and no allocation.
+ * Its scratch (per-edge activations and per-chunk partial gradients, about
+ * 12.7 MB for the maximum) is a fixed array in device memory that each GPU
+ * holds from the first call on it until the process ends.
+ *   bf16_params_dev  ACO_MLP_PARAMS FP32 values that are BF16 roundings
+ *   feats_dev, y_dev count x 3 features and count targets (as the trainer's)
+ *   count            1 <= count <= ACO_MLP_NOALLOC_MAX_EDGES
+ *   grad_dev         out: ACO_MLP_PARAMS FP32, the mean-loss gradient
+ *   loss_dev         out: one FP64 mean loss, or NULL
+ *   hip_stream       enqueues here; it must belong to the current device
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (on different streams or threads without ordering) race and give wrong
+ * results.  Calls on one stream are ordered and safe.
+ * Errors: ACO_EINVAL for a NULL input or output, count out of range, or a
+ * stream of another device; ACO_EDEVICE for HIP errors. */
+#define ACO_MLP_NOALLOC_MAX_EDGES 16384
+aco_status aco_mlp_gradient_noalloc(const float* bf16_params_dev, const float* feats_dev,
+                                    const float* y_dev, int32_t count, float* grad_dev,
+                                    double* loss_dev, void* hip_stream);
+
 /* Diagnostic: write the deviates r_j, j = 0..count-1, that ant a draws at step
  * s of iteration t (see the header comment) to out_dev (device, count FP32),
  * on hip_stream.  Errors: ACO_EINVAL for count < 0. */

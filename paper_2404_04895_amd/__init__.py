@@ -17,7 +17,7 @@ from ._native import (BATCH_SORTED_MAX_N, SCHED_AUTO, SCHED_G16, SCHED_G32, SCHE
                       AcoError, AcoParams, BatchView, ScheduleEntry, check, lib)
 
 __all__ = ["Colony", "Batch", "MlpTrainer", "edge_ranks", "mlp_eta", "mlp_features",
-           "mlp_targets", "mlp_round", "MLP_PARAMS", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
+           "mlp_targets", "mlp_round", "mlp_gradient_noalloc", "MLP_PARAMS", "AcoError", "uniforms", "gamma_schedule", "workspace_bytes",
            "leading_dim", "MAX_CITIES", "SCHEDULES", "SCHED_AUTO", "SCHED_SORTED",
            "SORTED_SCHEDULES", "BATCH_SORTED_MAX_N"]
 
@@ -509,3 +509,15 @@ class MlpTrainer:
         check(lib().aco_mlp_trainer_params(self._t, _ptr(master), _ptr(eff)),
               "aco_mlp_trainer_params")
         return master, eff
+
+
+def mlp_gradient_noalloc(bf16_params, feats, y, grad_out, loss_out=None, stream=None):
+    """aco_mlp_gradient_noalloc: the gradient of the mean loss at BF16
+    parameters into grad_out (and the mean loss into loss_out), with no device
+    allocation in the library or here.  Every argument is a contiguous CUDA
+    tensor already: bf16_params, feats (count, 3), y, grad_out float32,
+    loss_out one float64 or None."""
+    check(lib().aco_mlp_gradient_noalloc(_ptr(bf16_params), _ptr(feats), _ptr(y),
+                                         feats.shape[0], _ptr(grad_out),
+                                         None if loss_out is None else _ptr(loss_out),
+                                         _stream_handle(stream)), "aco_mlp_gradient_noalloc")

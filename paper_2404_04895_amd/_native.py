@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "ACO_OK", -1: "ACO_EINVAL", -2: "ACO_ENOMEM", -3: "ACO_EDEVIC
                 -4: "ACO_ESTATE"}
 MAX_CITIES = 16384
 MLP_PARAMS = 4481
+MLP_NOALLOC_MAX_EDGES = 16384
 
 
 class AcoParams(ctypes.Structure):
@@ -105,6 +106,7 @@ SIGNATURES = {
     "aco_mlp_trainer_params": (_i32, [_vp, _vp, _vp]),
     "aco_mlp_trainer_loss": (_i32, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "aco_mlp_trainer_destroy": (None, [_vp]),
+    "aco_mlp_gradient_noalloc": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "aco_sync": (_i32, [_vp]),
     "aco_destroy": (None, [_vp]),
     "aco_last_error": (ctypes.c_char_p, []),

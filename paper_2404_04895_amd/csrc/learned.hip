@@ -38,7 +38,7 @@ namespace {
 constexpr int kH = 64;
 constexpr int OFF_W1 = 0, OFF_B1 = 192, OFF_W2 = 256, OFF_B2 = 4352, OFF_W3 = 4416,
               OFF_B3 = 4480;
-constexpr int kChunk = 64;  // edges per workgroup in the backward pass
+constexpr int kChunk = kMlpChunk;  // edges per workgroup in the backward pass
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));

@@ -7,6 +7,7 @@
 namespace aco {
 
 constexpr int kMlpParams = 4481;  // W1[64][3], b1[64], W2[64][64], b2[64], W3[64], b3
+constexpr int kMlpChunk = 64;     // edges per workgroup of the backward pass (one partial each)
 
 int32_t mlp_rank_pow2(int32_t n);
 int32_t mlp_chunks(int32_t count);

@@ -1,6 +1,7 @@
 // C ABI of the learned edge heuristic (declared in include/aco.h).
 #include <math.h>
 
+#include <mutex>
 #include <new>
 
 #include "aco.h"
@@ -44,6 +45,73 @@ TrainerLayout trainer_layout(int32_t batch) {
     L.loss = take(sizeof(double));
     L.total = off;
     return L;
+}
+
+// ---- aco_mlp_gradient_noalloc: scratch in a fixed per-GPU array ----------------
+// The gradient's scratch (per-edge activations z, h1, a2; per-chunk partial
+// gradients and losses; the mean loss when the caller passes no loss buffer)
+// for up to ACO_MLP_NOALLOC_MAX_EDGES edges.  Every GPU the library runs on
+// holds its own copy for the life of the process.
+constexpr size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct NoAllocLayout {
+    size_t z, h1, a2, partial, partial_loss, loss, total;
+};
+
+constexpr NoAllocLayout noalloc_layout() {
+    constexpr size_t E = ACO_MLP_NOALLOC_MAX_EDGES;
+    constexpr size_t chunks = (E + aco::kMlpChunk - 1) / aco::kMlpChunk;
+    NoAllocLayout L{};
+    L.z = 0;
+    L.h1 = up256(L.z + sizeof(float) * E);
+    L.a2 = up256(L.h1 + sizeof(float) * 64 * E);
+    L.partial = up256(L.a2 + sizeof(float) * 64 * E);
+    L.partial_loss = up256(L.partial + sizeof(float) * aco::kMlpParams * chunks);
+    L.loss = up256(L.partial_loss + sizeof(double) * chunks);
+    L.total = up256(L.loss + sizeof(double));
+    return L;
+}
+
+constexpr NoAllocLayout kNoAlloc = noalloc_layout();
+// whole 32-edge forward tiles of the largest input stay inside z, h1 and a2
+static_assert(ACO_MLP_NOALLOC_MAX_EDGES % 64 == 0, "maximum must be whole tiles and chunks");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` on each GPU
+
+}  // namespace
+
+// Device memory of aco_mlp_gradient_noalloc.  In host code this name is only
+// a handle for hipGetSymbolAddress, never a device address.
+static __device__ __align__(256) char scratch[kNoAlloc.total];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device.
+aco_status noalloc_scratch(hipStream_t stream, char** out) {
+    int dev = 0;
+    ACO_HIP(hipGetDevice(&dev), "aco_mlp_gradient_noalloc: current device");
+    if (stream) {
+        hipDevice_t sdev = 0;
+        ACO_HIP(hipStreamGetDevice(stream, &sdev), "aco_mlp_gradient_noalloc: stream device");
+        if (sdev != dev)
+            return fail(ACO_EINVAL,
+                        "aco_mlp_gradient_noalloc: the stream is on device %d but device %d is "
+                        "current; make the stream's device current", static_cast<int>(sdev), dev);
+    }
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ACO_EINVAL, "aco_mlp_gradient_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        ACO_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+                "aco_mlp_gradient_noalloc: scratch address");
+        if (!p) return fail(ACO_EDEVICE, "aco_mlp_gradient_noalloc: scratch address is NULL");
+        g_scratch_dev[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return ACO_OK;
 }
 
 }  // namespace
@@ -242,5 +310,35 @@ aco_status aco_mlp_trainer_loss(aco_mlp_trainer* t, double* loss_host) {
 }
 
 void aco_mlp_trainer_destroy(aco_mlp_trainer* t) { delete t; }
+
+aco_status aco_mlp_gradient_noalloc(const float* bf16_params_dev, const float* feats_dev,
+                                    const float* y_dev, int32_t count, float* grad_dev,
+                                    double* loss_dev, void* hip_stream) {
+    if (!bf16_params_dev || !feats_dev || !y_dev || !grad_dev)
+        return fail(ACO_EINVAL, "aco_mlp_gradient_noalloc: NULL pointer");
+    if (count < 1 || count > ACO_MLP_NOALLOC_MAX_EDGES)
+        return fail(ACO_EINVAL, "aco_mlp_gradient_noalloc: count = %d outside [1, %d]", count,
+                    ACO_MLP_NOALLOC_MAX_EDGES);
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    char* ws = nullptr;
+    if (aco_status st = noalloc_scratch(stream, &ws)) return st;
+    float* z = reinterpret_cast<float*>(ws + kNoAlloc.z);
+    float* h1 = reinterpret_cast<float*>(ws + kNoAlloc.h1);
+    float* a2 = reinterpret_cast<float*>(ws + kNoAlloc.a2);
+    float* partial = reinterpret_cast<float*>(ws + kNoAlloc.partial);
+    double* partial_loss = reinterpret_cast<double*>(ws + kNoAlloc.partial_loss);
+    double* loss = loss_dev ? loss_dev : reinterpret_cast<double*>(ws + kNoAlloc.loss);
+    // every value the kernels read from the scratch is written earlier in the
+    // same call, so nothing needs clearing
+    ACO_HIP(aco::launch_forward_train(bf16_params_dev, feats_dev, count, z, h1, a2, stream),
+            "aco_mlp_gradient_noalloc: forward");
+    ACO_HIP(aco::launch_backward(bf16_params_dev, feats_dev, y_dev, z, h1, a2, count, partial,
+                                 partial_loss, stream),
+            "aco_mlp_gradient_noalloc: backward");
+    ACO_HIP(aco::launch_reduce_adam(partial, partial_loss, count, grad_dev, loss, nullptr, nullptr,
+                                    nullptr, nullptr, false, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, stream),
+            "aco_mlp_gradient_noalloc: reduce");
+    return ACO_OK;
+}
 
 }  // extern "C"
