@@ -15,6 +15,7 @@ LIB = os.path.join(HERE, "libaco.so")
 SOURCES = ["api.hip", "batch_api.hip", "construct.hip", "sorted.hip", "update.hip",
            "learned.hip", "learned_api.hip"]
 ARCH = os.environ.get("ACO_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -39,7 +40,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src, p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed on " + src)
-    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    # roctx ranges around the C-ABI calls (rocprofv3 --marker-trace shows them)
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", LIB + ".tmp",
+           "-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -357,6 +357,7 @@ aco_status aco_set_sorted_walk(aco_ctx* ctx, int32_t batches) {
 }
 
 aco_status aco_transition(aco_ctx* ctx, float gamma) {
+    const aco::TraceRange trace("aco_transition");
     if (aco_status st = check_ctx(ctx)) return st;
     if (!finite_positive(gamma)) return fail(ACO_EINVAL, "aco_transition: gamma <= 0");
     if (aco_status st = bind_device(ctx)) return st;
@@ -370,6 +371,7 @@ aco_status aco_transition(aco_ctx* ctx, float gamma) {
 }
 
 aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) {
+    const aco::TraceRange trace("aco_construct");
     if (aco_status st = check_ctx(ctx)) return st;
     if (m < 1 || m > ctx->m_max)
         return fail(ACO_EINVAL, "aco_construct: m = %d outside [1, %d]", m, ctx->m_max);
@@ -393,6 +395,7 @@ aco_status aco_construct(aco_ctx* ctx, int32_t m, uint64_t seed, uint32_t iter) 
 }
 
 aco_status aco_update(aco_ctx* ctx, float gamma_next) {
+    const aco::TraceRange trace("aco_update");
     if (aco_status st = check_ctx(ctx)) return st;
     if (!finite_positive(gamma_next)) return fail(ACO_EINVAL, "aco_update: gamma <= 0");
     if (!ctx->have_tours) return fail(ACO_ESTATE, "aco_update: no construct since last update");
@@ -414,6 +417,7 @@ aco_status aco_update(aco_ctx* ctx, float gamma_next) {
 
 aco_status aco_run(aco_ctx* ctx, int32_t m, uint64_t seed, int32_t iters,
                    int32_t* best_tour_host, float* best_len_host) {
+    const aco::TraceRange trace("aco_run");
     if (aco_status st = check_ctx(ctx)) return st;
     if (iters < 0) return fail(ACO_EINVAL, "aco_run: iters < 0");
     if (m < 1 || m > ctx->m_max)

@@ -409,6 +409,7 @@ aco_status aco_batch_set_schedules(aco_batch* b, const aco_schedule_entry* table
 }
 
 aco_status aco_batch_run(aco_batch* b, int32_t iters, int32_t flags) {
+    const aco::TraceRange trace("aco_batch_run");
     if (!b) return fail(ACO_EINVAL, "null batch");
     if (iters < 0 || iters > kMaxRunIters)
         return fail(ACO_EINVAL, "aco_batch_run: iters outside [0, %d]", kMaxRunIters);

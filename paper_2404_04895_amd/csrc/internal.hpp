@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -11,6 +12,17 @@
 #define ACO_LDS_ROW_MAX ACO_MAX_CITIES
 
 namespace aco {
+
+// A named roctx range over the host side of one C-ABI call (it encloses the
+// enqueueing of that call's kernels), so that a kernel trace taken with
+// rocprofv3 --marker-trace shows which call launched what.  Without a
+// profiler attached a push and a pop are two cheap library calls.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Best-so-far record kept on the device (written by the best-tour kernel).
 struct BestRecord {
