@@ -19,6 +19,18 @@ bytes are what the kernel reports it read: 6 B per sorted entry, 16 B per
 block of a fallback scan, 8 B per step.  roofline_full_scan
 = the same for the full scan, timed on the same colony right after.
 cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+roofline_issue = the same construct launches against the chip's VALU issue
+capacity, from committed SQ_INSTS_VALU counts of the same kernel source
+(omitted when the source has changed since they were taken).
+
+On the default workload the line also carries the rest of the metric, each
+object measured on its own workload after the headline:
+  full_run  all 200 iterations of the 5000-city run, one gamma schedule
+  batched   512 instances of 50..500 cities, graph replay (its own roofline
+            and CPU baseline)
+  learned   the learned heuristic against eta = 1/d at equal wall time on
+            held-out clustered 2000-city instances (% shorter best tour)
+--no-extras leaves them out.
 """
 import argparse
 import hashlib
@@ -34,6 +46,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
 COUNTERS_FILES = {"adair": os.path.join(ROOT, "profiles", "construct_counters.json"),
                   "adair-sorted": os.path.join(ROOT, "profiles", "construct_sorted_counters.json")}
 SORTED_MIN_N = 400     # the sorted walk loses at 159 cities and wins at 442 (m = n)
+DEFAULT_WORKLOAD = "clustered-n5000-m5000"
+BATCH_WORKLOAD = "batched-512-uniform-n50-500"
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles
+# on a 16-lane SIMD, at 2.4 GHz
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
+SQ_COUNTERS_FILES = {"adair-sorted": os.path.join(ROOT, "profiles",
+                                                  "construct_sorted_sq_counters.json")}
 KERNEL_SOURCES = ["paper_2404_04895_amd/csrc/construct.hip", "paper_2404_04895_amd/csrc/construct.hpp",
                   "paper_2404_04895_amd/csrc/philox.hpp"]
 
@@ -81,6 +100,29 @@ def counter_traffic(n, m, selection="adair"):
     if c.get("source_hash") != construct_source_hash() or c.get("n") != n or c.get("m") != m:
         return None
     return c.get("bytes_per_launch")
+
+
+def issue_rate(n, m, selection, avg_construct_s):
+    """VALU issue rate of the construct against the chip's issue capacity,
+    from committed SQ_INSTS_VALU counts of the same kernel source and
+    workload (None otherwise)."""
+    path = SQ_COUNTERS_FILES.get(selection)
+    if path is None:
+        return None
+    try:
+        with open(path) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != construct_source_hash() or c.get("n") != n or c.get("m") != m:
+        return None
+    valu = c["valu_insts_per_launch"]
+    achieved = valu / avg_construct_s / 1e9
+    return {"bound": "alu", "kernel": c["kernel"], "achieved": achieved,
+            "peak": VALU_ISSUE_PEAK_G, "unit": "G VALU wave-instructions/s",
+            "frac": achieved / VALU_ISSUE_PEAK_G, "valu_insts_per_launch": valu,
+            "valu_insts_per_ant_step": valu / (m * (n - 1)),
+            "counters": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(w, D, P, budget_s=15.0):
@@ -154,7 +196,9 @@ def cpu_baseline_batch(w, dists, budget_s=15.0):
     }
 
 
-def bench_batch(args, w):
+def bench_batch(args, w, cpu_budget_s=15.0):
+    """The batched workload: `args.steps` iterations of every instance, graph
+    replay, timed whole; then as many again with each construct launch timed."""
     import numpy as np
     import torch
 
@@ -219,11 +263,11 @@ def bench_batch(args, w):
         "sorted_walk_members": int(sorted_member.sum()),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_batch(w, dists)
-    print(json.dumps(line), flush=True)
+        line["cpu_baseline"] = cpu_baseline_batch(w, dists, budget_s=cpu_budget_s)
+    return line
 
 
-def bench_learned(args):
+def bench_learned(args, count):
     """Learned eta against eta = 1/d at equal wall time on held-out clustered
     n = 2000 instances (30 Gaussians, sigma 0.015), m = n, 300 iterations."""
     import numpy as np
@@ -234,7 +278,7 @@ def bench_learned(args):
     if master is None:
         raise SystemExit("no trained weights")
     kappa, lam = learned.heuristic_config()
-    count = max(1, args.steps)
+    count = max(1, count)
     rows = learned.equal_time_comparison(learned.evaluation_instances(count), [0], master,
                                          kappa=kappa, lam=lam, verbose=False)
     gaps = np.array([r["gap"] for r in rows])
@@ -255,10 +299,57 @@ def bench_learned(args):
                    "m": 2000, "iters": 300, "alpha": 1.0, "beta": 2.0, "rho": 0.1,
                    "cities": "clustered, 30 Gaussians sigma 0.015", "kappa": kappa,
                    "lambda": lam},
-        "runs": [{k: r[k] for k in ("plain_len", "learned_len", "gap", "plain_s", "learned_s",
-                                    "learned_iters")} for r in rows],
+        "min_gap_percent": 100.0 * float(gaps.min()),
+        "better_runs": int((gaps > 0).sum()),
+        "target_percent": 2.0,
+        "runs": [{k: r[k] for k in ("instance", "plain_len", "learned_len", "gap", "plain_s",
+                                    "learned_s", "learned_iters")} for r in rows],
     }
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def bench_full_run(w, seed, selection):
+    """All `w.iters` iterations of the workload on a fresh colony, as one run
+    (the gamma schedule over the whole run): wall time per iteration, and the
+    construct launches timed by HIP events on the colony's stream."""
+    import torch
+
+    from paper_2404_04895_amd import Colony, gamma_schedule
+
+    D = w.dist(seed)
+    dev = torch.device("cuda:0")
+    col = Colony(torch.from_numpy(D).to(dev), w.alpha, w.beta, w.rho, w.Q, w.m, tau0=w.tau0,
+                 elite_k=w.elite_k, gamma_max=w.gamma_max, gamma_min=w.gamma_min)
+    col.set_selection(selection)
+    stream = torch.cuda.current_stream()
+    T = w.iters
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(T)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    col.transition(gamma_schedule(0, T, w.gamma_max, w.gamma_min))
+    for t in range(T):
+        events[t][0].record(stream)
+        col.construct(w.m, seed, t)
+        events[t][1].record(stream)
+        col.update(gamma_schedule(t + 1, T, w.gamma_max, w.gamma_min))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    construct_ms = [a.elapsed_time(b) for a, b in events]
+    _, best_len, best_iter = col.best()
+    col.close()
+    quarter = max(1, T // 4)
+    return {
+        "iterations": T,
+        "selection": selection,
+        "ms_per_iteration": elapsed / T * 1e3,
+        "ant_steps_per_s": w.m * (w.n - 1) * T / elapsed,
+        "construct_ms_mean": sum(construct_ms) / T,
+        "construct_ms_by_quarter": [sum(construct_ms[q * quarter:(q + 1) * quarter]) / quarter
+                                    for q in range(4)],
+        "best_len": best_len,
+        "best_iter": best_iter,
+    }
 
 
 def main():
@@ -266,7 +357,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clustered-n5000-m5000")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--selection", default=None,
@@ -284,6 +375,10 @@ def main():
                     help="MAX-MIN upper bound on tau")
     ap.add_argument("--walk", type=int, default=None,
                     help="sorted batches per step before the scan (adair-sorted)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload: no full run, batched or learned objects")
+    ap.add_argument("--learned-instances", type=int, default=5,
+                    help="held-out instances of the learned-vs-plain comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a "
                          "reference for HBM byte counters)")
@@ -300,10 +395,10 @@ def main():
     from paper_2404_04895_amd import Colony, gamma_schedule
 
     if args.workload in inst.BATCH_WORKLOADS:
-        bench_batch(args, inst.BATCH_WORKLOADS[args.workload])
+        print(json.dumps(bench_batch(args, inst.BATCH_WORKLOADS[args.workload])), flush=True)
         return
     if args.workload == "learned-clustered-n2000":
-        bench_learned(args)
+        print(json.dumps(bench_learned(args, args.steps)), flush=True)
         return
     w = inst.WORKLOADS[args.workload]
     n, m, T = w.n, w.m, w.iters
@@ -424,9 +519,20 @@ def main():
         line["sorted_walk"] = walk
     if reference is not None:
         line["roofline_full_scan"] = reference
+    issue = issue_rate(n, m, args.selection, avg_construct_s)
+    if issue is not None:
+        line["roofline_issue"] = issue
     col.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, D, P_host)
+    if not args.no_extras and w.name == DEFAULT_WORKLOAD:
+        # the rest of the metric, on the other workloads it is quoted on
+        line["full_run"] = bench_full_run(w, args.seed, args.selection)
+        print("full run done", file=sys.stderr, flush=True)
+        line["batched"] = bench_batch(args, inst.BATCH_WORKLOADS[BATCH_WORKLOAD],
+                                      cpu_budget_s=8.0)
+        print("batched done", file=sys.stderr, flush=True)
+        line["learned"] = bench_learned(args, args.learned_instances)
     print(json.dumps(line), flush=True)
 
 
