@@ -12,7 +12,14 @@ five repeats (run seeds 0-4), m = 500 ants, on one uniform instance.  The
 convergence generation of a run is the first iteration whose best-so-far is
 within 0.1% of the run's final best.
 
-    python -m paper_2404_04895_amd.ablation [--report FILE] [--quick]
+The paper names cosine annealing for gamma but no constants, so the
+convergence part also runs AdaIR under other schedules (gamma at the first
+iteration -> gamma at the last), greedier than IR where gamma < 1: the
+default 1.5 -> 1.0, 1.5 -> 0.5, 1.0 -> 0.5, the reverse 0.5 -> 1.0, and a
+constant 1.5.  Every schedule runs the same kernels; only P's exponent 1/gamma
+changes.
+
+    python -m paper_2404_04895_amd.ablation [--report FILE] [--quick] [--convergence-only]
 """
 import argparse
 import json
@@ -25,6 +32,13 @@ RULES = {
     "IR": dict(selection="adair", gamma_max=1.0, gamma_min=1.0),
     "AdaIR": dict(selection="adair", gamma_max=1.5, gamma_min=1.0),
 }
+# AdaIR under other gamma schedules (first -> last iteration): convergence only
+SCHEDULE_VARIANTS = {
+    "AdaIR 1.5->0.5": dict(selection="adair", gamma_max=1.5, gamma_min=0.5),
+    "AdaIR 1.0->0.5": dict(selection="adair", gamma_max=1.0, gamma_min=0.5),
+    "AdaIR 0.5->1.0": dict(selection="adair", gamma_max=0.5, gamma_min=1.0),
+    "AdaIR 1.5 const": dict(selection="adair", gamma_max=1.5, gamma_min=1.5),
+}
 # AdaIR's exact sorted walk: the same tours as "AdaIR", so it is timed but its
 # convergence is AdaIR's
 TIMED_ONLY = {"AdaIR-sorted": dict(selection="adair-sorted", gamma_max=1.5, gamma_min=1.0)}
@@ -35,7 +49,7 @@ def _colony(D, rule, m, alpha=1.0, beta=2.0, rho=0.1):
     import torch
 
     from . import Colony
-    spec = RULES.get(rule) or TIMED_ONLY[rule]
+    spec = RULES.get(rule) or SCHEDULE_VARIANTS.get(rule) or TIMED_ONLY[rule]
     col = Colony(torch.from_numpy(D).cuda(), alpha, beta, rho, 1.0, m,
                  gamma_max=spec["gamma_max"], gamma_min=spec["gamma_min"])
     col.set_selection(spec["selection"])
@@ -64,7 +78,7 @@ def best_so_far_curve(D, rule, m, iters, seed):
 
     from . import gamma_schedule
     col = _colony(D, rule, m)
-    spec = RULES[rule]
+    spec = RULES.get(rule) or SCHEDULE_VARIANTS[rule]
     g = lambda t: gamma_schedule(t, iters, spec["gamma_max"], spec["gamma_min"])
     col.transition(g(0))
     mins = []
@@ -87,10 +101,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--report", default=None)
     ap.add_argument("--quick", action="store_true", help="fewer iterations, for a smoke run")
+    ap.add_argument("--convergence-only", action="store_true", help="skip the runtime part")
     args = ap.parse_args()
     iters, repeats = (200, 2) if args.quick else (1000, 5)
     report = {"runtime_ms_per_iteration": {}, "convergence": {}}
-    for n in RUNTIME_SIZES:
+    for n in (() if args.convergence_only else RUNTIME_SIZES):
         D = inst.distance_matrix(inst.uniform_cities(n, 5000 + n))
         times = iteration_times(D, n)
         times["speedup_AdaIR_over_RW"] = times["RW"] / times["AdaIR"]
@@ -102,11 +117,13 @@ def main():
                 times["speedup_AdaIR_over_RW"], times["speedup_AdaIR_sorted_over_RW"]), flush=True)
     n_conv, m_conv = 442, 500
     D = inst.distance_matrix(inst.uniform_cities(n_conv, 5442))
-    for rule in RULES:
+    for rule in list(RULES) + list(SCHEDULE_VARIANTS):
         curves = [best_so_far_curve(D, rule, m_conv, iters, s) for s in range(repeats)]
         gens = [convergence_generation(c) for c in curves]
         finals = [float(c[-1]) for c in curves]
+        spec = RULES.get(rule) or SCHEDULE_VARIANTS[rule]
         report["convergence"][rule] = {
+            "gamma_first": spec["gamma_max"], "gamma_last": spec["gamma_min"],
             "n": n_conv, "m": m_conv, "iterations": iters, "repeats": repeats,
             "generation": gens, "final_best": finals,
             "mean_generation": float(np.mean(gens)), "mean_final_best": float(np.mean(finals)),
