@@ -405,25 +405,66 @@ __device__ __forceinline__ float4 matrix_block(__amdgpu_buffer_rsrc_t R, uint32_
 struct SortedSpec {
     int32_t city;  // same on every lane of the group
     float p;       // this lane's entry of the batch
-    int32_t j;
+    int32_t j;     // its city; -1 (with p = 0) for a lane past the row's end
 };
 
+// -1 if x has a bit set, else 0.  For wave-uniform x (a ballot), so the
+// compare and the select stay on the scalar unit.
+__device__ __forceinline__ uint32_t scalar_any(uint32_t x) {
+    uint32_t r;
+    asm("s_cmp_lg_u32 %1, 0\n\ts_cselect_b32 %0, -1, 0" : "=s"(r) : "s"(x) : "scc");
+    return r;
+}
+
+// Lane mask of the groups (G lanes each) that have a bit set in `ballot`.
+template <int G>
+__device__ __forceinline__ uint64_t groups_with_any(uint64_t ballot) {
+    const uint32_t lo = static_cast<uint32_t>(ballot);
+    const uint32_t hi = static_cast<uint32_t>(ballot >> 32);
+    if constexpr (G == kWave) {
+        const uint64_t a = scalar_any(lo | hi);
+        return a | (a << 32);
+    } else if constexpr (G == 32) {
+        return static_cast<uint64_t>(scalar_any(lo)) | (static_cast<uint64_t>(scalar_any(hi)) << 32);
+    } else {
+        static_assert(G == 16, "groups of 16, 32 or 64 lanes");
+        const uint32_t l = (scalar_any(lo & 0xFFFFu) & 0xFFFFu) | (scalar_any(lo >> 16) & 0xFFFF0000u);
+        const uint32_t h = (scalar_any(hi & 0xFFFFu) & 0xFFFFu) | (scalar_any(hi >> 16) & 0xFFFF0000u);
+        return static_cast<uint64_t>(l) | (static_cast<uint64_t>(h) << 32);
+    }
+}
+
+// Whether any lane of the calling lane's group has its bit set in `ballot`.
+template <int G>
+__device__ __forceinline__ bool group_any(uint64_t ballot) {
+    return __builtin_amdgcn_inverse_ballot_w64(groups_with_any<G>(ballot));
+}
+
 // v of the first lane of the calling lane's group whose bit is set in
-// `ballot`, or -1 if none is set; the lane indices are wave-uniform, so this
-// is scalar work and readlanes.
+// `ballot`, or -1 if none is set.  The lane indices are wave-uniform: per
+// group a scalar find-first and one readlane, then a select by group.
 template <int G>
 __device__ __forceinline__ int32_t group_first(uint64_t ballot, int32_t v) {
-    const int32_t g = (threadIdx.x & (kWave - 1)) / G;
-    int32_t r = -1;
+    if constexpr (G == kWave) {
+        const int32_t t = __builtin_amdgcn_readlane(v, __builtin_ctzll(ballot | (1ull << 63)));
+        return t | static_cast<int32_t>(~scalar_any(static_cast<uint32_t>(ballot) |
+                                                    static_cast<uint32_t>(ballot >> 32)));
+    } else {
+        constexpr int32_t kGroups = kWave / G;
+        constexpr uint32_t kMask = (G == 32) ? 0xFFFFFFFFu : ((1u << (G & 31)) - 1u);
+        int32_t r = 0;
 #pragma unroll
-    for (int32_t q = 0; q < kWave / G; ++q) {
-        const uint64_t bits = (G == kWave) ? ballot : ((ballot >> (q * G)) & ((1ull << (G & 63)) - 1ull));
-        if (bits) {
-            const int32_t t = __builtin_amdgcn_readlane(v, q * G + __builtin_ctzll(bits));
-            if (g == q) r = t;
+        for (int32_t q = 0; q < kGroups; ++q) {
+            const uint32_t bits = static_cast<uint32_t>(ballot >> (q * G)) & kMask;
+            // an empty group reads its last lane; the OR then makes it -1
+            const int32_t first = __builtin_ctz(bits | (1u << (G - 1)));
+            const int32_t t = __builtin_amdgcn_readlane(v, q * G + first) |
+                              static_cast<int32_t>(~scalar_any(bits));
+            const uint64_t group_q = (G == 32 ? 0xFFFFFFFFull : ((1ull << G) - 1ull)) << (q * G);
+            r = (q == 0 || __builtin_amdgcn_inverse_ballot_w64(group_q)) ? t : r;
         }
+        return r;
     }
-    return r;
 }
 
 // Sorted walk of one step of group g: read the row's entries in descending
@@ -442,9 +483,12 @@ __device__ __forceinline__ int32_t group_first(uint64_t ballot, int32_t v) {
 template <int G>
 __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cur,
                                                const uint32_t* visited, int32_t gl, int32_t s,
-                                               int32_t ant, uint32_t& entries_read,
+                                               const PhiloxAnt& pant, uint32_t& entries_read,
                                                SortedSpec& spec) {
     const SortedRows R = sorted_rows(I);
+    // the deviates' counter words shared by every candidate of this step
+    const PhiloxStep pstep = philox_step(pant, static_cast<uint32_t>(s), I.key1);
+    const uint32_t iter_k1 = I.iter ^ I.key1;
     const uint32_t off = __umul24(static_cast<uint32_t>(cur), static_cast<uint32_t>(I.sorted_ld));
     int32_t best_key = -1;
     int32_t best_j = 0x7FFFFFFF;
@@ -460,21 +504,20 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
         const int32_t pos = base + gl;
         float p = 0.0f;
         int32_t j = -1;
-        if (pos < limit) {
-            if (base == 0 && ahead) {
-                p = spec.p;
-                j = spec.j;
-            } else {
-                p = sorted_p(R, off + pos);
-                j = sorted_j(R, off + pos);
-            }
+        if (base == 0 && ahead) {
+            // a lane at or past the limit never loads a speculative entry and
+            // keeps the empty one (0, -1)
+            p = spec.p;
+            j = spec.j;
+        } else if (pos < limit) {
+            p = sorted_p(R, off + pos);
+            j = sorted_j(R, off + pos);
         }
-        // an empty lane (j = -1) reads word 0 and is then dropped, so the
-        // test needs no branch
-        const int32_t jw = max(j, 0);
-        const bool cand = (j >= 0) & !((visited[jw >> 5] >> (jw & 31)) & 1u);
+        // an empty lane (j = -1) reads bit 31 of the guard word, which is
+        // set, so the test needs no branch and no range check
+        const bool cand = !((visited[j >> 5] >> (j & 31)) & 1u);
         if (base == 0) {
-            spec.city = group_first<G>(__ballot(cand), j);
+            spec.city = group_first<G>(__builtin_amdgcn_ballot_w64(cand), j);
             if (spec.city >= 0 && gl < limit) {
                 const uint32_t next =
                     __umul24(static_cast<uint32_t>(spec.city), static_cast<uint32_t>(I.sorted_ld)) + gl;
@@ -484,16 +527,15 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
             __builtin_amdgcn_s_setprio(0);
         }
         if (cand) {
-            const PhiloxOut r = philox10_block(static_cast<uint32_t>(j >> 2),
-                                               static_cast<uint32_t>(s),
-                                               static_cast<uint32_t>(ant), I.iter, I.key0,
-                                               I.key1);
+            const PhiloxOut r = philox10_candidate(static_cast<uint32_t>(j >> 2), pstep,
+                                                   iter_k1, I.key0, I.key1);
             // word j mod 4 of the block's four, picked without a branch
             const uint32_t w01 = (j & 1) ? r.w1 : r.w0;
             const uint32_t w23 = (j & 1) ? r.w3 : r.w2;
             const uint32_t w = (j & 2) ? w23 : w01;
             const int32_t key = score_key(p, w, 0u);
-            if (key > best_key || (key == best_key && j < best_j)) {
+            // a lane's first candidate needs no compare: scores are >= +0
+            if (base == 0 || key > best_key || (key == best_key && j < best_j)) {
                 best_key = key;
                 best_j = j;
             }
@@ -502,8 +544,12 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
         // the decision gates the next step: ahead of other deviates too
         __builtin_amdgcn_s_setprio(1);
         const int32_t top = group_reduce<G, true>(best_key);
-        const float p_last = __int_as_float(group_lane<G>(__float_as_int(p), G - 1));
-        if (top >= 0 && p_last < __int_as_float(top))
+        // the batch's last entry has its smallest P, so some entry below the
+        // best score is the same as the last one below it; an empty lane
+        // (P = 0, only at the end of a row) is below any positive score, as
+        // the missing entries after it are
+        const bool below = group_any<G>(__builtin_amdgcn_ballot_w64(p < __int_as_float(top)));
+        if (top >= 0 && below)
             return group_reduce<G, false>(best_key == top ? best_j : 0x7FFFFFFF);
     }
     return -1;
@@ -522,13 +568,13 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     const int32_t nwords = mask_words(nblk);
     uint32_t* area = lds + g * group_lds_words(n, LIVE, G);
     double* lengths_window = reinterpret_cast<double*>(area);
-    uint32_t* visited = area + 2 * G;
+    uint32_t* visited = area + 2 * G + 1;  // visited[-1] is the guard word
     uint16_t* live = reinterpret_cast<uint16_t*>(visited + nwords);
 
-    for (int32_t w = gl; w < nwords; w += G) {
+    for (int32_t w = gl - 1; w < nwords; w += G) {
         const int32_t j0 = w * 32;
         uint32_t bits = 0u;
-        if (j0 + 32 > n) bits = (j0 >= n) ? 0xFFFFFFFFu : (0xFFFFFFFFu << (n - j0));
+        if (w < 0 || j0 + 32 > n) bits = (w < 0 || j0 >= n) ? 0xFFFFFFFFu : (0xFFFFFFFFu << (n - j0));
         visited[w] = bits;
     }
     if constexpr (LIVE) {
@@ -536,7 +582,8 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     }
     int32_t nlive = nblk;
     uint32_t walk_entries = 0, scanned_steps = 0, scanned_blocks = 0;
-    SortedSpec spec{-1, 0.0f, 0};
+    SortedSpec spec{-1, 0.0f, -1};
+    const PhiloxAnt pant = philox_ant(static_cast<uint32_t>(ant), I.key0);
     __builtin_amdgcn_wave_barrier();
 
     // Start city (Sec. 2.2 initialization): word 0 of counter (0, 0, ant, iter).
@@ -554,7 +601,7 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         int32_t walked = -1;
         if constexpr (SEL == kSelSorted) {
             if (s > 0) {
-                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, ant, walk_entries, spec));
+                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, pant, walk_entries, spec));
             }
         }
         if (SEL == kSelRoulette && s > 0) {

@@ -96,6 +96,78 @@ __device__ __forceinline__ PhiloxOut philox10_block(uint32_t block, uint32_t ste
     return PhiloxOut{x0, x1, x2, x3};
 }
 
+// Philox4x32-10 for the counters (block, step, ant, iter) of one ant's step,
+// where only `block` differs between the candidates.  Rounds 0 and 1 multiply
+// the ant word and the step's word 0 by the same constants for every
+// candidate, so those products are taken once: per ant (PhiloxAnt, for the
+// whole tour) and per step (PhiloxStep, for every batch of the step).  What
+// remains per candidate is one multiply in rounds 0 and 1, two from round 2
+// on, and a two- or three-input XOR per new word.  The outputs are the same
+// four words as philox10_block's.
+struct PhiloxAnt {
+    uint32_t h;   // hi(ant * kMulB) ^ k0: word 0 after round 0 is h ^ step
+    uint32_t u1;  // lo(ant * kMulB): word 1 after round 0
+};
+
+struct PhiloxStep {
+    uint32_t u1;   // word 1 after round 0 (the ant's)
+    uint32_t v1;   // hi(word 0 after round 0 * kMulA) ^ round-1 key 1: word 2 after round 1 is word 3 ^ v1
+    uint32_t v2;   // lo(word 0 after round 0 * kMulA) ^ round-2 key 1, folded into word 2 after round 2
+};
+
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxBumpA = 0x9E3779B9u;
+constexpr uint32_t kPhiloxBumpB = 0xBB67AE85u;
+
+__device__ __forceinline__ PhiloxAnt philox_ant(uint32_t ant, uint32_t k0) {
+    const uint64_t pb = static_cast<uint64_t>(ant) * kPhiloxMulB;
+    return PhiloxAnt{static_cast<uint32_t>(pb >> 32) ^ k0, static_cast<uint32_t>(pb)};
+}
+
+__device__ __forceinline__ PhiloxStep philox_step(const PhiloxAnt& a, uint32_t step,
+                                                  uint32_t k1) {
+    const uint64_t pa = static_cast<uint64_t>(a.h ^ step) * kPhiloxMulA;
+    return PhiloxStep{a.u1, static_cast<uint32_t>(pa >> 32) ^ (k1 + kPhiloxBumpB),
+                      static_cast<uint32_t>(pa) ^ (k1 + 2u * kPhiloxBumpB)};
+}
+
+// `iter_k1` is iter ^ k1 (wave-uniform).
+__device__ __forceinline__ PhiloxOut philox10_candidate(uint32_t block, const PhiloxStep& st,
+                                                       uint32_t iter_k1, uint32_t k0,
+                                                       uint32_t k1) {
+    // round 0: word 0 and word 1 come from the ant and the step
+    const uint64_t pa0 = static_cast<uint64_t>(block) * kPhiloxMulA;
+    const uint32_t x2a = static_cast<uint32_t>(pa0 >> 32) ^ iter_k1;
+    const uint32_t x3a = static_cast<uint32_t>(pa0);
+    // round 1: word 0's product is the step's
+    const uint64_t pb1 = static_cast<uint64_t>(x2a) * kPhiloxMulB;
+    const uint32_t x0b = xor3_vvs(static_cast<uint32_t>(pb1 >> 32), st.u1, k0 + kPhiloxBumpA);
+    const uint32_t x1b = static_cast<uint32_t>(pb1);
+    const uint32_t x2b = x3a ^ st.v1;
+    // round 2: word 3 after round 1 is the step's
+    const uint64_t pa2 = static_cast<uint64_t>(x0b) * kPhiloxMulA;
+    const uint64_t pb2 = static_cast<uint64_t>(x2b) * kPhiloxMulB;
+    uint32_t x0 = xor3_vvs(static_cast<uint32_t>(pb2 >> 32), x1b, k0 + 2u * kPhiloxBumpA);
+    uint32_t x1 = static_cast<uint32_t>(pb2);
+    uint32_t x2 = static_cast<uint32_t>(pa2 >> 32) ^ st.v2;
+    uint32_t x3 = static_cast<uint32_t>(pa2);
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        const uint64_t pa = static_cast<uint64_t>(x0) * kPhiloxMulA;
+        const uint64_t pb = static_cast<uint64_t>(x2) * kPhiloxMulB;
+        const uint32_t n0 = xor3_vvs(static_cast<uint32_t>(pb >> 32), x1,
+                                     k0 + static_cast<uint32_t>(r) * kPhiloxBumpA);
+        const uint32_t n2 = xor3_vvs(static_cast<uint32_t>(pa >> 32), x3,
+                                     k1 + static_cast<uint32_t>(r) * kPhiloxBumpB);
+        x0 = n0;
+        x1 = static_cast<uint32_t>(pb);
+        x2 = n2;
+        x3 = static_cast<uint32_t>(pa);
+    }
+    return PhiloxOut{x0, x1, x2, x3};
+}
+
 // (2*(w >> 9) + 1) * 2^-24 without a conversion: OR the top 23 bits into the
 // mantissa of 1.0f, giving 1 + k*2^-23 in [1, 2), then subtract 1 - 2^-24.
 // The difference (2k+1)*2^-24 has at most 24 significant bits, so the FP32
