@@ -153,7 +153,7 @@ aco_status upload_tasks(aco_batch* b) {
         for (int32_t a = 0; a < in.m; a += per_wave)
             per[q].push_back(aco::BatchTask{i, a, std::min(per_wave, in.m - a), sched});
         load[q] += static_cast<double>(in.m) * (in.n - 1) * in.n;
-        lds = std::max(lds, aco::wave_lds_bytes(in.n, base));
+        lds = std::max(lds, aco::wave_lds_bytes(in.n, sched));
     }
     std::vector<aco::BatchTask> tasks;
     std::vector<int32_t> start(aco::kQueues + 1, 0);

@@ -480,7 +480,7 @@ __device__ __forceinline__ int32_t group_first(uint64_t ballot, int32_t v) {
 // as that entry is known, while the deviates are still being drawn; the next
 // step uses it if that city is taken.  Only where the data comes from
 // changes, not the result.
-template <int G>
+template <int G, bool BYTES>
 __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cur,
                                                const uint32_t* visited, int32_t gl, int32_t s,
                                                const PhiloxAnt& pant, uint32_t& entries_read,
@@ -513,9 +513,14 @@ __device__ __forceinline__ int32_t sorted_walk(const InstanceView& I, int32_t cu
             p = sorted_p(R, off + pos);
             j = sorted_j(R, off + pos);
         }
-        // an empty lane (j = -1) reads bit 31 of the guard word, which is
-        // set, so the test needs no branch and no range check
-        const bool cand = !((visited[j >> 5] >> (j & 31)) & 1u);
+        // an empty lane (j = -1) reads the last mark of the guard word, which
+        // is set, so the test needs no branch and no range check
+        bool cand;
+        if constexpr (BYTES) {
+            cand = reinterpret_cast<const uint8_t*>(visited)[j] == 0;
+        } else {
+            cand = !((visited[j >> 5] >> (j & 31)) & 1u);
+        }
         if (base == 0) {
             spec.city = group_first<G>(__builtin_amdgcn_ballot_w64(cand), j);
             if (spec.city >= 0 && gl < limit) {
@@ -564,17 +569,33 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
     if (g >= nants) return;  // whole groups idle; no lane of an active group depends on them
     const int32_t n = I.n;
     const int32_t ant = ant0 + g;
+    // the sorted walk without a live list marks visited cities by bytes
+    constexpr bool kBytes = SEL == kSelSorted && !LIVE;
     const int32_t nblk = (n + 3) >> 2;
-    const int32_t nwords = mask_words(nblk);
-    uint32_t* area = lds + g * group_lds_words(n, LIVE, G);
+    const int32_t nwords = kBytes ? nblk : mask_words(nblk);
+    uint32_t* area = lds + g * group_lds_words(n, LIVE, G, kBytes);
     double* lengths_window = reinterpret_cast<double*>(area);
     uint32_t* visited = area + 2 * G + 1;  // visited[-1] is the guard word
+    uint8_t* vmap = reinterpret_cast<uint8_t*>(visited);  // the byte marks (kBytes)
     uint16_t* live = reinterpret_cast<uint16_t*>(visited + nwords);
 
     for (int32_t w = gl - 1; w < nwords; w += G) {
-        const int32_t j0 = w * 32;
         uint32_t bits = 0u;
-        if (w < 0 || j0 + 32 > n) bits = (w < 0 || j0 >= n) ? 0xFFFFFFFFu : (0xFFFFFFFFu << (n - j0));
+        if constexpr (kBytes) {
+            // word w holds the marks of cities 4w .. 4w+3; cities at or past n
+            // (and the guard) are marked
+            if (w < 0) {
+                bits = 0x80808080u;
+            } else {
+#pragma unroll
+                for (int32_t k = 0; k < 4; ++k)
+                    if (4 * w + k >= n) bits |= 0x80u << (8 * k);
+            }
+        } else {
+            const int32_t j0 = w * 32;
+            if (w < 0 || j0 + 32 > n)
+                bits = (w < 0 || j0 >= n) ? 0xFFFFFFFFu : (0xFFFFFFFFu << (n - j0));
+        }
         visited[w] = bits;
     }
     if constexpr (LIVE) {
@@ -601,7 +622,8 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
         int32_t walked = -1;
         if constexpr (SEL == kSelSorted) {
             if (s > 0) {
-                walked = group_uniform<G>(sorted_walk<G>(I, cur, visited, gl, s, pant, walk_entries, spec));
+                walked = group_uniform<G>(sorted_walk<G, kBytes>(I, cur, visited, gl, s, pant,
+                                                                  walk_entries, spec));
             }
         }
         if (SEL == kSelRoulette && s > 0) {
@@ -628,11 +650,21 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
                                                    static_cast<uint32_t>(s),
                                                    static_cast<uint32_t>(ant), I.iter,
                                                    I.key0, I.key1);
-                const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
-                const int32_t k0 = score_key(p.x, r.w0, taken << 31);
-                const int32_t k1 = score_key(p.y, r.w1, (taken << 30) & 0x80000000u);
-                const int32_t k2 = score_key(p.z, r.w2, (taken << 29) & 0x80000000u);
-                const int32_t k3 = score_key(p.w, r.w3, (taken << 28) & 0x80000000u);
+                int32_t k0, k1, k2, k3;
+                if constexpr (kBytes) {
+                    // the block's four marks, 0x80 where visited
+                    const uint32_t taken = visited[b];
+                    k0 = score_key(p.x, r.w0, (taken << 24) & 0x80000000u);
+                    k1 = score_key(p.y, r.w1, (taken << 16) & 0x80000000u);
+                    k2 = score_key(p.z, r.w2, (taken << 8) & 0x80000000u);
+                    k3 = score_key(p.w, r.w3, taken & 0x80000000u);
+                } else {
+                    const uint32_t taken = visited[b >> 3] >> ((b & 7) << 2);
+                    k0 = score_key(p.x, r.w0, taken << 31);
+                    k1 = score_key(p.y, r.w1, (taken << 30) & 0x80000000u);
+                    k2 = score_key(p.z, r.w2, (taken << 29) & 0x80000000u);
+                    k3 = score_key(p.w, r.w3, (taken << 28) & 0x80000000u);
+                }
                 // block winner: strict compares keep the smaller city on ties
                 const int32_t e01 = (k1 > k0) ? 1 : 0;
                 const int32_t m01 = max(k0, k1);
@@ -691,6 +723,9 @@ __device__ void construct_group(const InstanceView& I, int32_t ant0, int32_t nan
             bits = visited[word] | (1u << (next & 31));
             __builtin_amdgcn_wave_barrier();
             if (gl == 0) visited[word] = bits;
+        } else if constexpr (kBytes) {
+            // one byte store; the wave's later LDS reads see it
+            if (gl == 0) vmap[next] = 0x80u;
         } else {
             // an LDS OR with no return value: nothing on the step's chain
             // waits for it, and the wave's later LDS reads see it
@@ -765,7 +800,8 @@ template <int G, bool LIVE>
 hipError_t launch_one(const InstanceView& I, int32_t m, int32_t selection, hipStream_t stream) {
     constexpr int32_t kGroups = kWave / G;
     const size_t lds = sizeof(uint32_t) * static_cast<size_t>(kGroups) *
-                       static_cast<size_t>(group_lds_words(I.n, LIVE, G));
+                       static_cast<size_t>(group_lds_words(I.n, LIVE, G,
+                                                           selection == kSelSorted && !LIVE));
     const dim3 grid((m + kGroups - 1) / kGroups);
     if (selection == kSelRoulette) {
         hipLaunchKernelGGL((construct_kernel<G, LIVE, kSelRoulette>), grid, dim3(kWave), lds,
@@ -905,8 +941,11 @@ int32_t sorted_default_schedule(int32_t m) {
 }
 
 size_t wave_lds_bytes(int32_t n, int32_t sched) {
-    return sizeof(uint32_t) * static_cast<size_t>(kWave / schedule_lanes(sched)) *
-           static_cast<size_t>(group_lds_words(n, schedule_live(sched), schedule_lanes(sched)));
+    const bool sorted = (sched & kSchedSorted) != 0;
+    const int32_t base = sched & ~kSchedSorted;
+    return sizeof(uint32_t) * static_cast<size_t>(kWave / schedule_lanes(base)) *
+           static_cast<size_t>(group_lds_words(n, schedule_live(base), schedule_lanes(base),
+                                               sorted && !schedule_live(base)));
 }
 
 bool roulette_fits(int32_t n, int32_t sched) {

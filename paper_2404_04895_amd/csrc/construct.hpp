@@ -43,12 +43,15 @@ __host__ __device__ constexpr int32_t mask_words(int32_t nblk) { return (nblk + 
 
 // LDS words one ant of a group of `lanes` lanes needs: the window of edge
 // lengths (one double per lane), a guard word with every bit set (the
-// visited bits of "city -1", an empty entry of the sorted walk), the visited
-// bitmask, then (optionally) the u16 list of live blocks; rounded up to 16
-// bytes, so that every group's window is aligned for 16-byte reads.
-__host__ __device__ constexpr int32_t group_lds_words(int32_t n, bool live, int32_t lanes) {
-    return (2 * lanes + 1 + mask_words((n + 3) >> 2) + (live ? (((n + 3) >> 2) + 1) / 2 : 0) +
-            3) & ~3;
+// visited mark of "city -1", an empty entry of the sorted walk), the visited
+// marks -- one bit per city, or one byte per city (`bytes`, the sorted walk
+// without a live list: its test is then one byte load) -- then (optionally)
+// the u16 list of live blocks; rounded up to 16 bytes, so that every group's
+// window is aligned for 16-byte reads.
+__host__ __device__ constexpr int32_t group_lds_words(int32_t n, bool live, int32_t lanes,
+                                                      bool bytes = false) {
+    return (2 * lanes + 1 + (bytes ? (n + 3) >> 2 : mask_words((n + 3) >> 2)) +
+            (live ? (((n + 3) >> 2) + 1) / 2 : 0) + 3) & ~3;
 }
 
 int32_t schedule_lanes(int32_t sched);
