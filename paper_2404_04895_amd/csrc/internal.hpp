@@ -24,6 +24,28 @@ struct TraceRange {
     TraceRange& operator=(const TraceRange&) = delete;
 };
 
+// Sum of x[0], ..., x[n-1] widened to FP64, added in ascending index order
+// (the sequential sum, bit for bit), by one workgroup: its threads stage
+// kOrderedSumChunk values at a time in `stage` (LDS), and thread 0 adds them
+// in order.  The result is valid in thread 0.
+constexpr int32_t kOrderedSumChunk = 1024;
+
+__device__ __forceinline__ double ordered_sum_f64(const float* __restrict__ x, int32_t n,
+                                                  double* stage) {
+    double total = 0.0;
+    for (int32_t base = 0; base < n; base += kOrderedSumChunk) {
+        const int32_t cnt = min(kOrderedSumChunk, n - base);
+        for (int32_t k = static_cast<int32_t>(threadIdx.x); k < cnt;
+             k += static_cast<int32_t>(blockDim.x))
+            stage[k] = static_cast<double>(x[base + k]);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int32_t k = 0; k < cnt; ++k) total += stage[k];
+        __syncthreads();
+    }
+    return total;
+}
+
 // Best-so-far record kept on the device (written by the best-tour kernel).
 struct BestRecord {
     float len;     // +inf before the first update

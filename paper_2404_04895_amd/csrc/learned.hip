@@ -216,10 +216,12 @@ __global__ __launch_bounds__(256) void rank_kernel(const float* __restrict__ dis
     }
 }
 
-__global__ void mean_kernel(const float* __restrict__ nn_dist, int32_t n, double* __restrict__ out) {
-    double total = 0.0;
-    for (int32_t i = 0; i < n; ++i) total += static_cast<double>(nn_dist[i]);
-    *out = total / static_cast<double>(n);
+// Mean nearest-neighbour distance: the FP64 sum in city order, over n.
+__global__ __launch_bounds__(256) void mean_kernel(const float* __restrict__ nn_dist, int32_t n,
+                                                   double* __restrict__ out) {
+    __shared__ double stage[kOrderedSumChunk];
+    const double total = ordered_sum_f64(nn_dist, n, stage);
+    if (threadIdx.x == 0) *out = total / static_cast<double>(n);
 }
 
 // ---- inference over every edge of an instance -------------------------------------
@@ -495,7 +497,7 @@ hipError_t launch_ranks(const float* dist, int32_t n, int32_t* rank, float* nn_d
                        dist, n, pow2, rank, nn_dist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(1), 0, stream, nn_dist, n, mean_nn);
+    hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, stream, nn_dist, n, mean_nn);
     return hipGetLastError();
 }
 

@@ -478,13 +478,13 @@ __global__ __launch_bounds__(256) void validate_kernel(const float* __restrict__
     }
 }
 
-// Sum of the row minima in ascending city order (one thread: the order is the
-// definition of the bound the quantisation exponent is derived from).
-__global__ void lower_bound_kernel(const float* __restrict__ row_min, int32_t n,
-                                   double* __restrict__ out) {
-    double total = 0.0;
-    for (int32_t i = 0; i < n; ++i) total += static_cast<double>(row_min[i]);
-    *out = total;
+// Sum of the row minima in ascending city order (the order is the definition
+// of the bound the quantisation exponent is derived from).
+__global__ __launch_bounds__(256) void lower_bound_kernel(const float* __restrict__ row_min,
+                                                          int32_t n, double* __restrict__ out) {
+    __shared__ double stage[kOrderedSumChunk];
+    const double total = ordered_sum_f64(row_min, n, stage);
+    if (threadIdx.x == 0) *out = total;
 }
 
 // ---- batched engine kernels -------------------------------------------------
@@ -605,7 +605,7 @@ hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, 
                        is_distance ? 1 : 0, is_distance ? 1 : 0, row_min, flags);
     e = hipGetLastError();
     if (e != hipSuccess || !lower_bound) return e;
-    hipLaunchKernelGGL(lower_bound_kernel, dim3(1), dim3(1), 0, stream, row_min, n, lower_bound);
+    hipLaunchKernelGGL(lower_bound_kernel, dim3(1), dim3(256), 0, stream, row_min, n, lower_bound);
     return hipGetLastError();
 }
 
