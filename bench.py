@@ -377,7 +377,7 @@ def main():
                     help="sorted batches per step before the scan (adair-sorted)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload: no full run, batched or learned objects")
-    ap.add_argument("--learned-instances", type=int, default=5,
+    ap.add_argument("--learned-instances", type=int, default=10,
                     help="held-out instances of the learned-vs-plain comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (a "

@@ -189,18 +189,19 @@ def equal_time_comparison(dists, run_seeds, master, iters=300, alpha=1.0, beta=2
     return rows
 
 
-def validate_kappa(master, kappas=(0.7, 1.0, 1.4, 2.0, 2.8), lam=DEFAULT_LAMBDA, count=6,
-                   seeds=(0, 1, 2), iters=300, verbose=True):
-    """Choose kappa on validation instances (clustered n = 2000, instance seeds
-    3000 on, never the evaluation seeds) by the mean relative gap to the plain
-    method over the same iteration count.  The runs use the sorted walk, which
-    builds the same tours as the full scan, only faster."""
+def validate_heuristic(master, kappas=(0.7, 1.0, 1.4, 2.0, 2.8), lams=(DEFAULT_LAMBDA,),
+                       count=6, seeds=(0, 1, 2), iters=300, verbose=True):
+    """Choose (kappa, lambda) on validation instances (clustered n = 2000,
+    instance seeds 3000 on, never the evaluation seeds) by the mean relative
+    gap to the plain method over the same iteration count.  The runs use the
+    sorted walk, which builds the same tours as the full scan, only faster."""
     import torch
 
     from . import Colony
     dists = evaluation_instances(count, seed0=3000)
-    gaps = {k: [] for k in kappas}
-    for D in dists:
+    grid = [(k, l) for k in kappas for l in lams]
+    gaps = {kl: [] for kl in grid}
+    for i, D in enumerate(dists):
         dev = torch.from_numpy(D).cuda()
         n = D.shape[0]
         for seed in seeds:
@@ -208,19 +209,21 @@ def validate_kappa(master, kappas=(0.7, 1.0, 1.4, 2.0, 2.8), lam=DEFAULT_LAMBDA,
             col.set_selection("adair-sorted")
             _, L_plain = col.run(n, seed, iters)
             col.close()
-            for k in kappas:
+            for k, l in grid:
                 col = Colony(dev, 1.0, 2.0, 0.1, 1.0, n)
                 col.set_selection("adair-sorted")
-                eta, _ = learned_eta(dev, master, k, lam)
+                eta, _ = learned_eta(dev, master, k, l)
                 col.set_eta(eta)
                 _, L = col.run(n, seed, iters)
                 col.close()
-                gaps[k].append((L_plain - L) / L_plain)
-    means = {k: float(np.mean(v)) for k, v in gaps.items()}
+                gaps[(k, l)].append((L_plain - L) / L_plain)
+        if verbose:
+            print("validation instance %d of %d done" % (i + 1, len(dists)), flush=True)
+    means = {kl: float(np.mean(v)) for kl, v in gaps.items()}
     if verbose:
-        for k in kappas:
-            print("validation kappa %.2f: mean gap %+.2f%% over %d runs" % (
-                k, 100 * means[k], len(gaps[k])), flush=True)
+        for k, l in grid:
+            print("validation kappa %.2f lambda %.2f: mean gap %+.2f%% over %d runs" % (
+                k, l, 100 * means[(k, l)], len(gaps[(k, l)])), flush=True)
     return max(means, key=means.get), means
 
 
@@ -242,8 +245,14 @@ def main():
     ap.add_argument("--instances", type=int, default=10)
     ap.add_argument("--seeds", type=int, default=3)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--record", action="store_true",
+                    help="evaluate: store the summary beside the weights")
     ap.add_argument("--train-iters", type=int, default=300)
     ap.add_argument("--runs", type=int, default=1)
+    ap.add_argument("--kappas", default="0.7,1.0,1.4,2.0,2.8",
+                    help="validate: exponents of the network's output to try")
+    ap.add_argument("--lambdas", default="1.0",
+                    help="validate: exponents of the scaled inverse distance to try")
     args = ap.parse_args()
     if args.mode == "train":
         feats, y = training_set(iters=args.train_iters, runs=args.runs)
@@ -258,12 +267,21 @@ def main():
     elif args.mode == "validate":
         master = load_weights(args.weights)
         assert master is not None, "no weights at " + args.weights
-        kappa, means = validate_kappa(master)
-        with open(args.weights.replace(".npy", ".json"), "w") as f:
-            json.dump({"kappa": kappa, "lambda": DEFAULT_LAMBDA,
-                       "validation_mean_gap": {str(k): v for k, v in means.items()}}, f,
-                      indent=1)
-        print("chose kappa %.2f" % kappa, flush=True)
+        kappas = [float(x) for x in args.kappas.split(",")]
+        lams = [float(x) for x in args.lambdas.split(",")]
+        (kappa, lam), means = validate_heuristic(master, kappas, lams)
+        # the choice and the grid go beside the weights; other records there stay
+        cfg_path = args.weights.replace(".npy", ".json")
+        try:
+            with open(cfg_path) as f:
+                cfg = json.load(f)
+        except (OSError, ValueError):
+            cfg = {}
+        cfg.update({"kappa": kappa, "lambda": lam,
+                    "validation_mean_gap": {"%g,%g" % kl: v for kl, v in means.items()}})
+        with open(cfg_path, "w") as f:
+            json.dump(cfg, f, indent=1)
+        print("chose kappa %.2f lambda %.2f" % (kappa, lam), flush=True)
     elif args.mode == "profile":
         # inference alone (ranks, features, network, eta) on the first held-out instance
         import torch
@@ -290,6 +308,18 @@ def main():
         if args.report:
             with open(args.report, "w") as f:
                 json.dump(rows, f, indent=1)
+        if args.record:
+            cfg_path = args.weights.replace(".npy", ".json")
+            with open(cfg_path) as f:
+                cfg = json.load(f)
+            cfg["held_out_equal_time"] = {
+                "mean_gap": float(gaps.mean()), "min_gap": float(gaps.min()),
+                "max_gap": float(gaps.max()), "better": int((gaps > 0).sum()),
+                "runs": len(rows), "kappa": kappa, "lambda": lam,
+                "instances": "clustered n = 2000, seeds 2000-%d x run seeds 0-%d" % (
+                    2000 + args.instances - 1, args.seeds - 1)}
+            with open(cfg_path, "w") as f:
+                json.dump(cfg, f, indent=1)
 
 
 if __name__ == "__main__":
