@@ -19,7 +19,12 @@ default 1.5 -> 1.0, 1.5 -> 0.5, 1.0 -> 0.5, the reverse 0.5 -> 1.0, and a
 constant 1.5.  Every schedule runs the same kernels; only P's exponent 1/gamma
 changes.
 
+With TSPLIB files at hand, `--tsplib FILE...` times the runtime part on them
+instead of the uniform stand-ins, and `--convergence-tsplib FILE` runs the
+convergence part on that instance (the paper's has 442 cities).
+
     python -m paper_2404_04895_amd.ablation [--report FILE] [--quick] [--convergence-only]
+        [--tsplib FILE_OR_DIR ...] [--convergence-tsplib FILE] [--tsplib-metric euclidean|tsplib]
 """
 import argparse
 import json
@@ -102,21 +107,44 @@ def main():
     ap.add_argument("--report", default=None)
     ap.add_argument("--quick", action="store_true", help="fewer iterations, for a smoke run")
     ap.add_argument("--convergence-only", action="store_true", help="skip the runtime part")
+    ap.add_argument("--tsplib", nargs="+", default=None,
+                    help="TSPLIB files (or directories of *.tsp) for the runtime part")
+    ap.add_argument("--convergence-tsplib", default=None,
+                    help="TSPLIB file for the convergence part")
+    ap.add_argument("--tsplib-metric", default="euclidean", choices=["euclidean", "tsplib"],
+                    help="distances of TSPLIB instances: plain Euclidean (default) or the "
+                         "file's integer metric")
     args = ap.parse_args()
     iters, repeats = (200, 2) if args.quick else (1000, 5)
     report = {"runtime_ms_per_iteration": {}, "convergence": {}}
-    for n in (() if args.convergence_only else RUNTIME_SIZES):
-        D = inst.distance_matrix(inst.uniform_cities(n, 5000 + n))
+    if args.tsplib:
+        from aco_instances import tsplib
+        runtime = []
+        for path in tsplib.instance_files(args.tsplib):
+            t = tsplib.read_tsplib(path)
+            runtime.append((t.name or path, tsplib.distance_matrix(t, args.tsplib_metric)))
+    else:
+        runtime = [(n, None) for n in RUNTIME_SIZES]
+    for label, D in (() if args.convergence_only else runtime):
+        if D is None:
+            D = inst.distance_matrix(inst.uniform_cities(label, 5000 + label))
+        n = D.shape[0]
         times = iteration_times(D, n)
         times["speedup_AdaIR_over_RW"] = times["RW"] / times["AdaIR"]
         times["speedup_AdaIR_sorted_over_RW"] = times["RW"] / times["AdaIR-sorted"]
-        report["runtime_ms_per_iteration"][n] = times
-        print("n=%d m=%d: " % (n, n) + "  ".join(
+        report["runtime_ms_per_iteration"][label] = times
+        print("%s: n=%d m=%d: " % (label, n, n) + "  ".join(
             "%s %.3f ms" % (k, v) for k, v in times.items() if not k.startswith("speedup")) +
             "  RW/AdaIR %.2fx  RW/AdaIR-sorted %.2fx" % (
                 times["speedup_AdaIR_over_RW"], times["speedup_AdaIR_sorted_over_RW"]), flush=True)
-    n_conv, m_conv = 442, 500
-    D = inst.distance_matrix(inst.uniform_cities(n_conv, 5442))
+    if args.convergence_tsplib:
+        from aco_instances import tsplib
+        D = tsplib.distance_matrix(tsplib.read_tsplib(args.convergence_tsplib),
+                                   args.tsplib_metric)
+        report["convergence_instance"] = args.convergence_tsplib
+    else:
+        D = inst.distance_matrix(inst.uniform_cities(442, 5442))
+    n_conv, m_conv = D.shape[0], 500
     for rule in list(RULES) + list(SCHEDULE_VARIANTS):
         curves = [best_so_far_curve(D, rule, m_conv, iters, s) for s in range(repeats)]
         gens = [convergence_generation(c) for c in curves]
