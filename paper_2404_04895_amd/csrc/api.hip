@@ -401,10 +401,9 @@ aco_status aco_update(aco_ctx* ctx, float gamma_next) {
     if (!ctx->have_tours) return fail(ACO_ESTATE, "aco_update: no construct since last update");
     if (aco_status st = bind_device(ctx)) return st;
     const int32_t m = ctx->last_m;
-    ACO_HIP(aco::launch_best(ctx->buf, ctx->n, m, ctx->last_iter, ctx->stream), "best");
-    ACO_HIP(aco::launch_deposit_weights(ctx->buf, m, ctx->params.elite_k, ctx->Q, ctx->S,
-                                        ctx->stream),
-            "deposit weights");
+    ACO_HIP(aco::launch_ants(ctx->buf, ctx->n, m, ctx->last_iter, ctx->params.elite_k, ctx->Q,
+                             ctx->S, ctx->stream),
+            "best and deposit weights");
     ACO_HIP(aco::launch_rows(ctx->buf, ctx->n, ctx->ld, m, ctx->m_max, true, ctx->eta_active,
                              ctx->alpha, ctx->beta, ctx->rho, ctx->S, gamma_next, ctx->tau_min,
                              ctx->tau_max, ctx->stream),

@@ -118,10 +118,10 @@ hipError_t launch_clear_counters(unsigned long long* c, int32_t count, hipStream
 // Whether schedule `sched` can run the Roulette Wheel at n cities: the
 // running totals of the ceil(ceil(n/4)/G) chunks of a row live one per lane.
 bool roulette_fits(int32_t n, int32_t sched);
-hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, float Q,
-                                  int32_t S, hipStream_t stream);
-hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
-                       hipStream_t stream);
+// Deposit weights of the m ants (elite set of Sec. 2.3) and the best-so-far
+// record, one launch.
+hipError_t launch_ants(const Buffers& B, int32_t n, int32_t m, uint32_t iter, int32_t elite_k,
+                       float Q, int32_t S, hipStream_t stream);
 hipError_t launch_clear_best(BestRecord* best, int32_t count, hipStream_t stream);
 // tau_min, tau_max: MAX-MIN bounds applied after the update (0, +inf: none).
 hipError_t launch_rows(const Buffers& B, int32_t n, int32_t ld, int32_t m, int32_t m_max,

@@ -339,12 +339,6 @@ __device__ __forceinline__ int64_t ant_weight(const float* lengths, int32_t a, i
     return elite ? __double2ll_rn((Q / static_cast<double>(La)) * scale) : 0;
 }
 
-__global__ void weights_kernel(const float* __restrict__ lengths, int32_t m, int32_t elite_k,
-                               double Q, double scale, int64_t* __restrict__ weight) {
-    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= m) return;
-    weight[a] = ant_weight(lengths, a, m, elite_k, Q, scale);
-}
 
 // Best-so-far: the shortest tour of this iteration (ties to the smaller ant)
 // replaces the record only if strictly shorter.  T threads, one record.
@@ -401,12 +395,20 @@ __device__ void best_update(const float* __restrict__ lengths, const int32_t* __
     }
 }
 
-__global__ __launch_bounds__(1024) void best_kernel(const float* __restrict__ lengths,
+// The iteration's per-ant work before the row update, in one launch: every
+// ant's quantised deposit weight (all blocks, one thread per ant) and the
+// best-so-far record (block 0).  Both only read the lengths and tours, and
+// they write disjoint outputs.
+__global__ __launch_bounds__(1024) void ants_kernel(const float* __restrict__ lengths,
                                                     const int32_t* __restrict__ tours, int32_t n,
                                                     int32_t m, uint32_t iter,
                                                     BestRecord* __restrict__ best,
-                                                    int32_t* __restrict__ best_tour) {
-    best_update<1024>(lengths, tours, n, m, iter, best, best_tour);
+                                                    int32_t* __restrict__ best_tour,
+                                                    int32_t elite_k, double Q, double scale,
+                                                    int64_t* __restrict__ weight) {
+    const int32_t a = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (a < m) weight[a] = ant_weight(lengths, a, m, elite_k, Q, scale);
+    if (blockIdx.x == 0) best_update<1024>(lengths, tours, n, m, iter, best, best_tour);
 }
 
 __global__ void clear_best_kernel(BestRecord* best, int32_t count) {
@@ -609,17 +611,11 @@ hipError_t launch_validate(const float* mat_dense, int32_t n, bool is_distance, 
     return hipGetLastError();
 }
 
-hipError_t launch_deposit_weights(const Buffers& B, int32_t m, int32_t elite_k, float Q,
-                                  int32_t S, hipStream_t stream) {
-    hipLaunchKernelGGL(weights_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, B.lengths, m,
-                       elite_k, static_cast<double>(Q), ldexp(1.0, S), B.weight);
-    return hipGetLastError();
-}
-
-hipError_t launch_best(const Buffers& B, int32_t n, int32_t m, uint32_t iter,
-                       hipStream_t stream) {
-    hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, stream, B.lengths, B.tours, n, m,
-                       iter, B.best, B.best_tour);
+hipError_t launch_ants(const Buffers& B, int32_t n, int32_t m, uint32_t iter, int32_t elite_k,
+                       float Q, int32_t S, hipStream_t stream) {
+    hipLaunchKernelGGL(ants_kernel, dim3((m + 1023) / 1024), dim3(1024), 0, stream, B.lengths,
+                       B.tours, n, m, iter, B.best, B.best_tour, elite_k, static_cast<double>(Q),
+                       ldexp(1.0, S), B.weight);
     return hipGetLastError();
 }
 
