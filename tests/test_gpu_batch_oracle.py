@@ -94,3 +94,38 @@ def test_batch_members_equal_oracle_run(table_name):
         # the table puts members on all five full-scan schedules and all three
         # sorted-walk widths
         assert len(set(scheds)) == 8, scheds
+
+
+def test_batch_members_equal_oracle_run_under_the_greedier_schedule():
+    """The same check under the alternative gamma schedule (cosine 1.0 ->
+    0.5), for a few members spanning the schedule table (tiny, full scan,
+    sorted walk)."""
+    torch = _torch()
+    from paper_2404_04895_amd import Batch
+    from paper_2404_04895_amd.autotune import load_table
+    pick = [0, 4, 8, 11]  # n = 3, 65, 257, 497
+    ms, seeds, dists = _members()
+    ms = [ms[i] for i in pick]
+    seeds = [seeds[i] + 1 for i in pick]
+    dists = [dists[i] for i in pick]
+    table, waves = load_table()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = Batch(dists, ALPHA, BETA, RHO, Q, ants=ms, seeds=seeds, elite_k=ELITE_K,
+                  gamma_max=1.0, gamma_min=0.5, stream=stream)
+        b.set_schedules(table, waves)
+        b.run(T, use_graph=True)
+        lens, its, tours = b.best()
+        for k, D in enumerate(dists):
+            o = oracle.run(D, ms[k], ALPHA, BETA, RHO, Q, seeds[k], T,
+                           elite_k=min(ELITE_K, ms[k]), gamma_max=1.0, gamma_min=0.5)
+            tag = "member n=%d, m=%d, schedule %d" % (D.shape[0], ms[k], b.view(k).schedule)
+            assert lens[k] == np.float32(o["best_len"]), tag
+            assert its[k] == o["best_iter"], tag
+            assert np.array_equal(tours[k], o["best_tour"]), tag
+            assert np.array_equal(b.tau(k).cpu().numpy(), o["tau"]), tag
+            P = b.P(k).cpu().numpy().astype(np.float64)
+            Po = o["P"].astype(np.float64)
+            assert np.all(np.abs(P - Po) <= 1e-5 * np.abs(Po)), tag
+        b.close()
+    stream.synchronize()

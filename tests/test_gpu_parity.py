@@ -361,3 +361,22 @@ def test_full_size_sampled_clustered_n5000():
     assert np.array_equal(tau_gpu.view(np.uint32), tau_ref.view(np.uint32))
     assert_P_close(P_gpu, oracle.transition(tau_ref, D, w.alpha, w.beta, 1.4), "P n=5000")
     col.close()
+
+
+@pytest.mark.parametrize("selection", ["adair", "adair-sorted"])
+def test_free_run_matches_oracle_under_the_greedier_schedule(selection):
+    """The alternative gamma schedule the design discusses (cosine 1.0 -> 0.5,
+    so P is raised to powers up to 2): aco_run against oracle_run, best tour,
+    best length and pheromone bit for bit, under both AdaIR constructs."""
+    torch = _torch()
+    n, m, T = 60, 60, 24
+    D = inst.distance_matrix(inst.clustered_cities(n, 31, 4, 0.05))
+    col = _colony(D, 1.0, 2.0, 0.2, 1.0, m, gamma_max=1.0, gamma_min=0.5)
+    col.set_selection(selection)
+    tour, L = col.run(m, 9, T)
+    ref = oracle.run(D, m, 1.0, 2.0, 0.2, 1.0, 9, T, gamma_max=1.0, gamma_min=0.5)
+    assert L == np.float32(ref["best_len"])
+    assert np.array_equal(tour, ref["best_tour"])
+    assert np.array_equal(col.tau().cpu().numpy(), ref["tau"])
+    assert_P_close(col.P().cpu().numpy(), ref["P"], "gamma 1.0 -> 0.5, " + selection)
+    col.close()
