@@ -1,5 +1,6 @@
 """Edge inputs on the GPU, through the C ABI: no ants, no iterations, the
-smallest instance under every selection rule."""
+smallest instance under every selection rule, and distances far from the
+unit square's scale (TSPLIB-sized integer distances, and tiny ones)."""
 import math
 
 import numpy as np
@@ -57,4 +58,26 @@ def test_smallest_instance_every_rule(selection):
         assert np.array_equal(col.tours(m).cpu().numpy(), want)
         assert np.array_equal(col.lengths(m).cpu().numpy(), wlen)
         assert np.allclose(wlen, 2.0 + math.sqrt(2.0))
+    col.close()
+
+
+@pytest.mark.parametrize("scale,metric", [(1e4, "tsplib"), (1e-4, "euclidean")])
+def test_distance_scales_match_oracle(scale, metric):
+    """Tour lengths from about 1e-3 to 1e6: the deposit's fixed-point exponent
+    follows the lower bound on a tour, so the run still equals the oracle's
+    bit for bit.  The large case uses TSPLIB's integer metric, where equal
+    tour lengths (ties broken by ant index) are common."""
+    torch = _torch()
+    from aco_instances import tsplib
+    from paper_2404_04895_amd import Colony
+    xy = inst.uniform_cities(40, 404).astype(np.float64) * scale
+    D = tsplib.distance_matrix(tsplib.parse_tsplib(tsplib.format_tsplib("scaled", xy)), metric)
+    n = m = D.shape[0]
+    T = 15
+    col = Colony(torch.from_numpy(D).cuda(), 1.0, 2.0, 0.3, 1.0, m)
+    tour, L = col.run(m, 5, T)
+    ref = oracle.run(D, m, 1.0, 2.0, 0.3, 1.0, 5, T)
+    assert L == np.float32(ref["best_len"])
+    assert np.array_equal(tour, ref["best_tour"])
+    assert np.array_equal(col.tau().cpu().numpy(), ref["tau"])
     col.close()
