@@ -140,20 +140,14 @@ def _explicit_matrix(vals, n, fmt):
     row_of_col = {"UPPER_COL": "LOWER_ROW", "LOWER_COL": "UPPER_ROW",
                   "UPPER_DIAG_COL": "LOWER_DIAG_ROW", "LOWER_DIAG_COL": "UPPER_DIAG_ROW"}
     fmt = row_of_col.get(fmt, fmt)
-    diag = "DIAG" in fmt
-    pairs = []
-    for i in range(n):
-        if fmt.startswith("UPPER"):
-            cols = range(i if diag else i + 1, n)
-        else:
-            cols = range(0, i + 1 if diag else i)
-        pairs.extend((i, j) for j in cols)
-    if vals.size != len(pairs):
-        raise TsplibError("%s holds %d numbers, expected %d" % (fmt, vals.size, len(pairs)))
+    k = 0 if "DIAG" in fmt else 1
+    # the triangle's (row, column) pairs in row-major order
+    rows, cols = np.triu_indices(n, k) if fmt.startswith("UPPER") else np.tril_indices(n, -k)
+    if vals.size != rows.size:
+        raise TsplibError("%s holds %d numbers, expected %d" % (fmt, vals.size, rows.size))
     W = np.zeros((n, n), np.float64)
-    for (i, j), v in zip(pairs, vals):
-        W[i, j] = v
-        W[j, i] = v
+    W[rows, cols] = vals
+    W[cols, rows] = vals
     return W
 
 
