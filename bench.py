@@ -436,7 +436,6 @@ def main():
     for t in range(args.warmup):
         step(t)
     torch.cuda.synchronize()
-    P_host = col.P().cpu().numpy() if not args.no_cpu_baseline else None
 
     sorted_walk = args.selection == "adair-sorted"
     if sorted_walk:
@@ -522,6 +521,9 @@ def main():
     issue = issue_rate(n, m, args.selection, avg_construct_s)
     if issue is not None:
         line["roofline_issue"] = issue
+    # the oracle's sample reads P from the host; copied only now, so that no
+    # idle gap sits between the warm-up and the timed steps
+    P_host = col.P().cpu().numpy() if not args.no_cpu_baseline else None
     col.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, D, P_host)
